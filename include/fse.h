@@ -1,0 +1,200 @@
+/*
+ * fse.h -- C ABI of the MI355X implementation of Frequency Selective
+ * Extrapolation (FSE) with the optimized, parallel block processing order of
+ * Seiler & Kaup, "Optimized and Parallelized Processing Order for Improved
+ * Frequency Selective Signal Extrapolation".
+ *
+ * What the library computes (paper Section 2 and Section 3):
+ *   An 8-bit image is divided into blocks (Section 2).  Every block holding
+ *   lost samples is extrapolated from its extrapolation area L (the block plus
+ *   a frame of d samples): the weighting function of Eq. (2) is applied, the
+ *   model of Eq. (1) is generated from DFT basis functions (Section 4) by K
+ *   greedy iterations (select the basis function with the largest weighted
+ *   energy reduction, estimate its coefficient with orthogonality deficiency
+ *   compensation factor gamma), and the model's samples are inserted into the
+ *   lost part of the block.  Blocks are processed either in line-scan order
+ *   (Section 2) or in waves of mutually non-adjacent blocks chosen by
+ *   Algorithm 1 (Section 3, Eq. (3)); the blocks of one wave run concurrently.
+ *
+ *   Readings of points the paper leaves open, fixed by this ABI:
+ *   - basis phi_k[m,n] = exp(+j 2 pi (k1 m / fft_h + k2 n / fft_w)), L at the
+ *     top-left of the fft_h x fft_w grid; the output is the real part;
+ *   - selection = argmax over k of |P[k]|^2 (P = weighted DFT of the current
+ *     residual), ties to the smallest k1*fft_w + k2; coefficient increment =
+ *     gamma * P[u] / sum(w); exactly `iterations` iterations;
+ *   - neighbours = 8-neighbourhood; rim blocks count their missing
+ *     neighbours as not extrapolated (margin +3, corner +5); N_min is the
+ *     smallest non-negative count; the wave is filled in raster order;
+ *   - every block of a wave reads the image as it was at the start of the
+ *     wave; reconstructed samples are reused unquantized;
+ *   - lost output samples are rounded half-to-even and clamped to [0, 255].
+ *
+ * Threading: a plan is used by one host thread at a time, except that
+ * fse_submit and fse_poll may be called concurrently with each other.
+ * All functions return FSE_OK (0) or a negative FSE_ERR_* code; fse_poll may
+ * also return FSE_PENDING.
+ */
+#ifndef FSE_H
+#define FSE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FSE_OK 0
+#define FSE_PENDING 1
+#define FSE_ERR_INVALID (-1)     /* null pointer, parameter out of range */
+#define FSE_ERR_UNSUPPORTED (-2) /* valid request this build cannot run */
+#define FSE_ERR_NOMEM (-3)       /* can never fit the device memory budget */
+#define FSE_ERR_AGAIN (-4)       /* serving slots full right now; retry */
+#define FSE_ERR_DEVICE (-5)      /* HIP error; sticky for the plan */
+#define FSE_ERR_TICKET (-6)      /* unknown or already consumed ticket */
+
+typedef struct fse_plan_s *fse_plan_t; /* opaque, owned by the library */
+
+/* Block processing order: Algorithm 1 (Section 3) or line scan (Section 2). */
+enum { FSE_ORDER_OPTIMIZED = 0, FSE_ORDER_LINESCAN = 1 };
+
+/* Arithmetic of the per-block iteration. */
+enum {
+  FSE_FP64 = 0, /* spectra, weights, coefficients in double */
+  FSE_FP32 = 1  /* spectra and iteration in float; synthesis sums in double */
+};
+
+/* fse_params.flags */
+#define FSE_FLAG_DEVICE_PTRS 1 /* frame pointers are device pointers */
+
+typedef struct {
+  int32_t block_w, block_h; /* block size in samples, 1..64 (paper: 2..16) */
+  int32_t border_d;         /* frame width d around the block, >= 0 */
+  int32_t fft_w, fft_h;     /* basis grid; this build supports 64 x 64 */
+  double rho;               /* weighting decay of Eq. (2), in (0, 1] */
+  double delta;             /* reconstructed-area weight of Eq. (2), [0, 1] */
+  double gamma;             /* orthogonality deficiency compensation, (0, 1] */
+  int32_t iterations;       /* K, 1..FSE_MAX_ITERATIONS */
+  int32_t order;            /* FSE_ORDER_* */
+  int32_t precision;        /* FSE_FP64 or FSE_FP32 */
+  int32_t grid_off_x;       /* block grid shift, 0 <= off < block size: */
+  int32_t grid_off_y;       /*   block column j covers x in
+                               [j*block_w - grid_off_x, +block_w) */
+  double empty_fill;        /* value written when L has no support */
+  int64_t device_mem_budget;   /* bytes for serving frames; 0 = 4 GiB */
+  int32_t max_inflight_frames; /* serving slots; 0 = 64 */
+  int32_t flags;               /* FSE_FLAG_* */
+} fse_params;
+
+#define FSE_MAX_ITERATIONS 1024
+
+/* Per-frame statistics (filled when fse_frame.stats is not null). */
+typedef struct {
+  int32_t waves;            /* waves this frame needed */
+  int32_t lost_blocks;      /* blocks holding at least one lost sample */
+  int32_t max_wave_blocks;  /* largest wave of this frame */
+  int32_t reserved;
+  double latency_ms;        /* fse_submit -> completion (serving only) */
+} fse_stats;
+
+/* Per-block trace of the greedy iteration (filled when fse_frame.trace is
+ * not null).  Arrays are caller-owned with room for `capacity` blocks.  */
+typedef struct {
+  int32_t capacity;     /* in: slots available */
+  int32_t count;        /* out: lost blocks of the frame (may exceed capacity;
+                           only the first `capacity` are written) */
+  int32_t *block;       /* [capacity] block index bi * wb + bj */
+  int32_t *wave;        /* [capacity] wave of that block */
+  int32_t *u;           /* [capacity * iterations] selected k1*fft_w + k2 */
+  double *dc;           /* [capacity * iterations * 2] (re, im) increments */
+} fse_trace;
+
+typedef struct {
+  const uint8_t *image; /* height rows of `stride` bytes; lost values ignored */
+  int32_t width, height, stride;
+  const uint8_t *lost;  /* nonzero = lost sample */
+  int32_t lost_stride;
+  uint8_t *out;         /* result, may alias image; known samples copied */
+  int32_t out_stride;
+  float *out_f32;       /* nullable: unquantized result as float, width*height
+                           contiguous (known samples hold their input value) */
+  double *out_f64;      /* nullable: the same as double */
+  fse_trace *trace;     /* nullable, host memory */
+  fse_stats *stats;     /* nullable, host memory */
+} fse_frame;
+
+/*
+ * Create a plan: validates the parameters, allocates the per-plan tables on
+ * the current HIP device and takes the stream (a hipStream_t, nullable = the
+ * library's own stream; with FSE_FLAG_DEVICE_PTRS this should be the caller's
+ * stream so that device buffers are ordered with the caller's work).
+ * Errors: FSE_ERR_INVALID (p or out null, parameter out of range,
+ * block + 2d > fft), FSE_ERR_UNSUPPORTED (fft other than 64 x 64),
+ * FSE_ERR_DEVICE (no usable device).  On error *out is set to NULL.
+ */
+int32_t fse_plan(const fse_params *p, void *hip_stream, fse_plan_t *out);
+
+/* Destroy a plan: cancels queued serving frames, waits for in-flight work and
+ * frees every device and host resource.  NULL is accepted. */
+int32_t fse_plan_destroy(fse_plan_t plan);
+
+/*
+ * Conceal n frames synchronously (paper Section 2-3 as described above).
+ * n > 1 batches the frames: wave t of the call is the union of wave t of every
+ * frame, executed as one kernel launch, so each frame gets exactly the result
+ * it gets alone.  With FSE_FLAG_DEVICE_PTRS, image/lost/out/out_f32/out_f64
+ * are device pointers and the work is ordered on the plan's stream; the call
+ * still returns only when the result is complete.
+ * Errors: FSE_ERR_INVALID (null plan/frames/pointers, n < 1, sizes <= 0 or
+ * above 65535, strides smaller than width, a trace with device pointers),
+ * FSE_ERR_DEVICE.
+ */
+int32_t fse_conceal_image(fse_plan_t plan, const fse_frame *frames, int32_t n);
+
+/*
+ * Serving: submit one frame (host pointers only).  The input is copied before
+ * the call returns; out, out_f32, out_f64, trace and stats must stay valid
+ * until fse_poll reports FSE_OK for the ticket (or the plan is destroyed).
+ * Frames in flight are continuously batched: every launch runs the next wave
+ * of every admitted frame.  Frames are admitted as slots and device memory
+ * free up.  Errors: FSE_ERR_INVALID, FSE_ERR_NOMEM (frame larger than the
+ * whole budget), FSE_ERR_AGAIN (queue full: max_inflight_frames frames
+ * waiting and running), FSE_ERR_DEVICE.
+ */
+int32_t fse_submit(fse_plan_t plan, const fse_frame *frame, uint64_t *ticket);
+
+/*
+ * Wait up to timeout_us microseconds (0 = do not wait, <0 = wait forever) for
+ * a submitted frame.  Returns FSE_OK once (the ticket is then consumed),
+ * FSE_PENDING, FSE_ERR_TICKET or FSE_ERR_DEVICE.
+ */
+int32_t fse_poll(fse_plan_t plan, uint64_t ticket, int32_t timeout_us);
+
+/*
+ * Processing order only (paper Algorithm 1 / line scan) for a block grid of
+ * hb x wb blocks; lost[hb*wb] nonzero marks blocks with samples to
+ * extrapolate.  wave_of[hb*wb] receives the wave index (-1 for the other
+ * blocks); seq[hb*wb] (nullable) the lost blocks in processing order.
+ * Host-only; returns the number of waves (>= 0) or FSE_ERR_INVALID.
+ */
+int32_t fse_schedule(int32_t hb, int32_t wb, const uint8_t *lost, int32_t order,
+                     int32_t *wave_of, int32_t *seq);
+
+/* Device time of the wave kernels of the last fse_conceal_image call, summed
+ * over its launches and measured with HIP events on the plan's stream, and
+ * the number of those launches and of the blocks they processed. */
+typedef struct {
+  double kernel_ms;
+  int64_t launches;
+  int64_t blocks;
+  double total_ms;   /* host wall time of the call */
+} fse_call_stats;
+int32_t fse_last_call_stats(fse_plan_t plan, fse_call_stats *out);
+
+/* Static description of an error code. */
+const char *fse_strerror(int32_t code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FSE_H */

@@ -1,0 +1,342 @@
+"""MI355X implementation of Frequency Selective Extrapolation (FSE) with the
+optimized, parallel block processing order of Seiler & Kaup.
+
+This module is a thin ctypes binding of ``libfse.so`` (C ABI in
+``include/fse.h``): it marshals arguments and nothing else; every step of the
+extrapolation runs in the library's HIP kernels.  Importing the package does
+not load the library; the first call does, and raises if the library has not
+been built (``python -m paper_2207_00233_amd.build``) -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfse.so")
+
+FSE_OK = 0
+FSE_PENDING = 1
+FSE_ERR_INVALID = -1
+FSE_ERR_UNSUPPORTED = -2
+FSE_ERR_NOMEM = -3
+FSE_ERR_AGAIN = -4
+FSE_ERR_DEVICE = -5
+FSE_ERR_TICKET = -6
+
+FSE_ORDER_OPTIMIZED = 0
+FSE_ORDER_LINESCAN = 1
+FSE_FP64 = 0
+FSE_FP32 = 1
+FSE_FLAG_DEVICE_PTRS = 1
+
+EXPORTED = ("fse_plan", "fse_plan_destroy", "fse_conceal_image", "fse_submit",
+            "fse_poll", "fse_schedule", "fse_last_call_stats", "fse_strerror")
+
+
+class FseError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        msg = "unknown"
+        try:
+            msg = load().fse_strerror(code).decode()
+        except Exception:  # pragma: no cover
+            pass
+        super().__init__(f"{where}: {msg} ({code})")
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("block_w", ctypes.c_int32), ("block_h", ctypes.c_int32),
+        ("border_d", ctypes.c_int32),
+        ("fft_w", ctypes.c_int32), ("fft_h", ctypes.c_int32),
+        ("rho", ctypes.c_double), ("delta", ctypes.c_double),
+        ("gamma", ctypes.c_double),
+        ("iterations", ctypes.c_int32), ("order", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("grid_off_x", ctypes.c_int32), ("grid_off_y", ctypes.c_int32),
+        ("empty_fill", ctypes.c_double),
+        ("device_mem_budget", ctypes.c_int64),
+        ("max_inflight_frames", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
+    ]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("waves", ctypes.c_int32), ("lost_blocks", ctypes.c_int32),
+                ("max_wave_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("latency_ms", ctypes.c_double)]
+
+
+class _Trace(ctypes.Structure):
+    _fields_ = [("capacity", ctypes.c_int32), ("count", ctypes.c_int32),
+                ("block", ctypes.POINTER(ctypes.c_int32)),
+                ("wave", ctypes.POINTER(ctypes.c_int32)),
+                ("u", ctypes.POINTER(ctypes.c_int32)),
+                ("dc", ctypes.POINTER(ctypes.c_double))]
+
+
+class _Frame(ctypes.Structure):
+    _fields_ = [("image", ctypes.c_void_p), ("width", ctypes.c_int32),
+                ("height", ctypes.c_int32), ("stride", ctypes.c_int32),
+                ("lost", ctypes.c_void_p), ("lost_stride", ctypes.c_int32),
+                ("out", ctypes.c_void_p), ("out_stride", ctypes.c_int32),
+                ("out_f32", ctypes.c_void_p), ("out_f64", ctypes.c_void_p),
+                ("trace", ctypes.POINTER(_Trace)), ("stats", ctypes.POINTER(_Stats))]
+
+
+class _CallStats(ctypes.Structure):
+    _fields_ = [("kernel_ms", ctypes.c_double), ("launches", ctypes.c_int64),
+                ("blocks", ctypes.c_int64), ("total_ms", ctypes.c_double)]
+
+
+@dataclasses.dataclass
+class Params:
+    """Parameters of fse_plan (paper Section 4 defaults: d=16, rho=0.8,
+    delta=0.2, gamma=0.5, 200 iterations; 64x64 DFT basis)."""
+    block_w: int = 16
+    block_h: int = 16
+    border_d: int = 16
+    fft_w: int = 64
+    fft_h: int = 64
+    rho: float = 0.8
+    delta: float = 0.2
+    gamma: float = 0.5
+    iterations: int = 200
+    order: int = FSE_ORDER_OPTIMIZED
+    precision: int = FSE_FP32
+    grid_off_x: int = 0
+    grid_off_y: int = 0
+    empty_fill: float = 128.0
+    device_mem_budget: int = 0
+    max_inflight_frames: int = 0
+    flags: int = 0
+
+    def c(self) -> _Params:
+        return _Params(**dataclasses.asdict(self))
+
+
+_lib = None
+
+
+def load():
+    """Load libfse.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2207_00233_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    lib.fse_plan.argtypes = [P(_Params), ctypes.c_void_p, P(ctypes.c_void_p)]
+    lib.fse_plan.restype = ctypes.c_int32
+    lib.fse_plan_destroy.argtypes = [ctypes.c_void_p]
+    lib.fse_plan_destroy.restype = ctypes.c_int32
+    lib.fse_conceal_image.argtypes = [ctypes.c_void_p, P(_Frame), ctypes.c_int32]
+    lib.fse_conceal_image.restype = ctypes.c_int32
+    lib.fse_submit.argtypes = [ctypes.c_void_p, P(_Frame), P(ctypes.c_uint64)]
+    lib.fse_submit.restype = ctypes.c_int32
+    lib.fse_poll.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32]
+    lib.fse_poll.restype = ctypes.c_int32
+    lib.fse_schedule.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                 ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+    lib.fse_schedule.restype = ctypes.c_int32
+    lib.fse_last_call_stats.argtypes = [ctypes.c_void_p, P(_CallStats)]
+    lib.fse_last_call_stats.restype = ctypes.c_int32
+    lib.fse_strerror.argtypes = [ctypes.c_int32]
+    lib.fse_strerror.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, where: str) -> int:
+    if rc < 0:
+        raise FseError(rc, where)
+    return rc
+
+
+# ----------------------------------------------------------------- C-ABI calls
+
+def fse_plan(params: Params, hip_stream: Optional[int] = None) -> "Plan":
+    """Create a plan (``fse_plan``)."""
+    return Plan(params, hip_stream)
+
+
+def fse_schedule(lost_blocks: np.ndarray, order: int = FSE_ORDER_OPTIMIZED):
+    """Processing order of a block grid (``fse_schedule``): number of waves,
+    wave index per block (-1 = nothing to extrapolate), lost blocks in order."""
+    lib = load()
+    lb = np.ascontiguousarray(lost_blocks, dtype=np.uint8)
+    hb, wb = lb.shape
+    wave = np.zeros(hb * wb, np.int32)
+    seq = np.zeros(max(1, hb * wb), np.int32)
+    nw = _check(lib.fse_schedule(hb, wb, lb.ctypes.data, order, wave.ctypes.data,
+                                 seq.ctypes.data), "fse_schedule")
+    return nw, wave.reshape(hb, wb), seq[:int((lb != 0).sum())]
+
+
+@dataclasses.dataclass
+class Result:
+    out: np.ndarray                      # uint8 [H, W]
+    out_f: Optional[np.ndarray] = None   # float32/float64 [H, W] unquantized
+    waves: int = 0
+    lost_blocks: int = 0
+    max_wave_blocks: int = 0
+    latency_ms: float = 0.0
+    trace_block: Optional[np.ndarray] = None  # int32 [n]
+    trace_wave: Optional[np.ndarray] = None   # int32 [n]
+    trace_u: Optional[np.ndarray] = None      # int32 [n, K]
+    trace_dc: Optional[np.ndarray] = None     # complex128 [n, K]
+
+
+class _HostFrame:
+    """Keeps the numpy buffers of one fse_frame alive."""
+
+    def __init__(self, image, lost, want_float, precision, trace_cap, K):
+        self.image = np.ascontiguousarray(image, dtype=np.uint8)
+        self.lost = np.ascontiguousarray(lost, dtype=np.uint8)
+        if self.image.shape != self.lost.shape or self.image.ndim != 2:
+            raise ValueError("image and lost must be 2-D arrays of the same shape")
+        H, W = self.image.shape
+        self.out = np.zeros((H, W), np.uint8)
+        self.of32 = np.zeros((H, W), np.float32) if want_float and precision == FSE_FP32 else None
+        self.of64 = np.zeros((H, W), np.float64) if want_float and precision == FSE_FP64 else None
+        self.stats = _Stats()
+        self.trace = None
+        if trace_cap:
+            self.tb = np.zeros(trace_cap, np.int32)
+            self.tw = np.zeros(trace_cap, np.int32)
+            self.tu = np.zeros(trace_cap * K, np.int32)
+            self.tdc = np.zeros(trace_cap * K * 2, np.float64)
+            P = ctypes.POINTER
+            self.trace = _Trace(trace_cap, 0, self.tb.ctypes.data_as(P(ctypes.c_int32)),
+                                self.tw.ctypes.data_as(P(ctypes.c_int32)),
+                                self.tu.ctypes.data_as(P(ctypes.c_int32)),
+                                self.tdc.ctypes.data_as(P(ctypes.c_double)))
+        self.c = _Frame(self.image.ctypes.data, W, H, W, self.lost.ctypes.data, W,
+                        self.out.ctypes.data, W,
+                        self.of32.ctypes.data if self.of32 is not None else None,
+                        self.of64.ctypes.data if self.of64 is not None else None,
+                        ctypes.pointer(self.trace) if self.trace is not None else None,
+                        ctypes.pointer(self.stats))
+
+    def result(self, K) -> Result:
+        r = Result(self.out, self.of32 if self.of32 is not None else self.of64,
+                   self.stats.waves, self.stats.lost_blocks, self.stats.max_wave_blocks,
+                   self.stats.latency_ms)
+        if self.trace is not None:
+            n = min(self.trace.count, len(self.tb))
+            r.trace_block = self.tb[:n].copy()
+            r.trace_wave = self.tw[:n].copy()
+            r.trace_u = self.tu[:n * K].reshape(n, K).copy()
+            d = self.tdc[:n * K * 2]
+            r.trace_dc = (d[0::2] + 1j * d[1::2]).reshape(n, K)
+        return r
+
+
+class Plan:
+    """An fse_plan handle.  Use as a context manager or call close()."""
+
+    def __init__(self, params: Params, hip_stream: Optional[int] = None):
+        self.params = params
+        self._lib = load()
+        h = ctypes.c_void_p()
+        self._pc = params.c()
+        _check(self._lib.fse_plan(ctypes.byref(self._pc), hip_stream, ctypes.byref(h)), "fse_plan")
+        self.handle = h
+        self._pending = {}
+
+    def close(self):
+        if self.handle:
+            self._lib.fse_plan_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- fse_conceal_image ------------------------------------------------
+    def fse_conceal_image(self, images: Sequence[np.ndarray], losts: Sequence[np.ndarray],
+                          want_float: bool = False, trace: bool = False) -> List[Result]:
+        """Conceal host images (uint8) with host loss masks, as one batch."""
+        if self.params.flags & FSE_FLAG_DEVICE_PTRS:
+            raise ValueError("plan expects device pointers: use conceal_device")
+        K = self.params.iterations
+        hf = []
+        for im, ls in zip(images, losts):
+            cap = 0
+            if trace:
+                hb = -(-(im.shape[0] + self.params.grid_off_y) // self.params.block_h)
+                wb = -(-(im.shape[1] + self.params.grid_off_x) // self.params.block_w)
+                cap = hb * wb
+            hf.append(_HostFrame(im, ls, want_float, self.params.precision, cap, K))
+        arr = (_Frame * len(hf))(*[f.c for f in hf])
+        _check(self._lib.fse_conceal_image(self.handle, arr, len(hf)), "fse_conceal_image")
+        return [f.result(K) for f in hf]
+
+    def conceal_device(self, frames) -> None:
+        """Conceal frames whose buffers are device memory.  ``frames`` is a list
+        of dicts with integer device pointers and sizes: image, lost, out,
+        width, height (strides = width), optional out_f32 / out_f64."""
+        arr = (_Frame * len(frames))()
+        for i, f in enumerate(frames):
+            W, H = int(f["width"]), int(f["height"])
+            arr[i] = _Frame(f["image"], W, H, W, f["lost"], W, f["out"], W,
+                            f.get("out_f32"), f.get("out_f64"), None, None)
+        _check(self._lib.fse_conceal_image(self.handle, arr, len(frames)), "fse_conceal_image")
+
+    def last_call_stats(self) -> dict:
+        cs = _CallStats()
+        _check(self._lib.fse_last_call_stats(self.handle, ctypes.byref(cs)), "fse_last_call_stats")
+        return {"kernel_ms": cs.kernel_ms, "launches": cs.launches, "blocks": cs.blocks,
+                "total_ms": cs.total_ms}
+
+    # -- fse_submit / fse_poll ------------------------------------------------
+    def fse_submit(self, image: np.ndarray, lost: np.ndarray, want_float: bool = False,
+                   trace: bool = False) -> int:
+        """Submit one frame for asynchronous concealment; returns a ticket."""
+        K = self.params.iterations
+        cap = 0
+        if trace:
+            hb = -(-(image.shape[0] + self.params.grid_off_y) // self.params.block_h)
+            wb = -(-(image.shape[1] + self.params.grid_off_x) // self.params.block_w)
+            cap = hb * wb
+        f = _HostFrame(image, lost, want_float, self.params.precision, cap, K)
+        t = ctypes.c_uint64()
+        _check(self._lib.fse_submit(self.handle, ctypes.byref(f.c), ctypes.byref(t)), "fse_submit")
+        self._pending[t.value] = f
+        return t.value
+
+    def fse_poll(self, ticket: int, timeout_us: int = 0):
+        """FSE_PENDING, or the Result once the frame is done."""
+        rc = self._lib.fse_poll(self.handle, ctypes.c_uint64(ticket), int(timeout_us))
+        if rc == FSE_PENDING:
+            return FSE_PENDING
+        _check(rc, "fse_poll")
+        f = self._pending.pop(ticket)
+        return f.result(self.params.iterations)
+
+
+def fse_conceal_image(plan: Plan, images, losts, **kw) -> List[Result]:
+    return plan.fse_conceal_image(images, losts, **kw)
+
+
+def fse_submit(plan: Plan, image, lost, **kw) -> int:
+    return plan.fse_submit(image, lost, **kw)
+
+
+def fse_poll(plan: Plan, ticket: int, timeout_us: int = 0):
+    return plan.fse_poll(ticket, timeout_us)

@@ -1,0 +1,58 @@
+// fse_internal.h -- plan object and helpers shared by the host runtime files.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <mutex>
+#include <vector>
+
+#include "fse.h"
+
+namespace fse {
+
+// Grow-only device allocation.
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t cap = 0;
+  int reserve(size_t bytes);
+  void release();
+};
+
+// Grow-only pinned host allocation.
+struct HostBuf {
+  void* ptr = nullptr;
+  size_t cap = 0;
+  int reserve(size_t bytes);
+  void release();
+};
+
+struct Serving;
+
+int validate_params(const fse_params* p);
+int validate_frame(const fse_frame* f, bool device_ptrs);
+
+}  // namespace fse
+
+struct fse_plan_s {
+  fse_params p;
+  int M = 0, N = 0, device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::vector<double> radial;  // M*N, rho^dist (Eq. (2))
+  std::vector<double> twid;    // 64 x (cos, sin)(2 pi t / 64)
+  fse::DevBuf tbl_radial, tbl_twid, tbl_twid64;
+  fse::DevBuf work, state, frames_dev, items_dev, u8_img, u8_lost, u8_out, fout, staging,
+      trace_u, trace_dc, flags_dev;
+  std::vector<hipEvent_t> events;
+  fse_call_stats last{};
+  int sticky = 0;
+  std::mutex exec_mu;  // one synchronous call at a time
+  fse::Serving* serving = nullptr;
+};
+
+namespace fse {
+int conceal_batch(fse_plan_s* pl, const fse_frame* frames, int n);
+int serving_init(fse_plan_s* pl);
+void serving_shutdown(fse_plan_s* pl);
+}  // namespace fse

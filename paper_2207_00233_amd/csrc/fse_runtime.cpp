@@ -1,0 +1,526 @@
+// fse_runtime.cpp -- host runtime and C ABI of the FSE library (fse.h).
+//
+// A plan owns the per-plan tables (radial weights of Eq. (2), DFT twiddles),
+// a HIP stream and grow-only device arenas.  fse_conceal_image runs the
+// paper's processing order (fse_sched.cpp) on the host and launches one fused
+// kernel per wave (fse_kernels.hip); with several frames, wave t of the call
+// is the union of wave t of every frame, so one launch covers all of them.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "fse.h"
+#include "fse_device.h"
+#include "fse_internal.h"
+#include "fse_sched.h"
+
+namespace fse {
+
+template <typename T>
+hipError_t launch_block(const BlockArgs<T>& a, int n_items, size_t lds, hipStream_t s);
+template <typename T>
+hipError_t launch_scatter(T* work, uint8_t* state, const FrameDesc* frames, const int32_t* items,
+                          int n_items, const T* staging, int Bh, int Bw, int gox, int goy,
+                          hipStream_t s);
+template <typename T>
+hipError_t launch_init(const uint8_t* image, int stride, const uint8_t* lost, int lstride,
+                       T* work, uint8_t* state, int H, int W, hipStream_t s);
+hipError_t launch_block_flags(const uint8_t* lost, int lstride, int H, int W, int Bh, int Bw,
+                              int gox, int goy, int hb, int wb, uint8_t* flags, hipStream_t s);
+template <typename T>
+hipError_t launch_finalize(const uint8_t* image, int stride, const uint8_t* state,
+                           const T* work, uint8_t* out, int ostride, float* of32, double* of64,
+                           int H, int W, hipStream_t s);
+
+int DevBuf::reserve(size_t bytes) {
+  if (bytes <= cap) return FSE_OK;
+  if (ptr) (void)hipFree(ptr);
+  ptr = nullptr;
+  cap = 0;
+  size_t want = bytes + bytes / 4 + 256;
+  if (hipMalloc(&ptr, want) != hipSuccess) {
+    ptr = nullptr;
+    return FSE_ERR_DEVICE;
+  }
+  cap = want;
+  return FSE_OK;
+}
+
+void DevBuf::release() {
+  if (ptr) (void)hipFree(ptr);
+  ptr = nullptr;
+  cap = 0;
+}
+
+int HostBuf::reserve(size_t bytes) {
+  if (bytes <= cap) return FSE_OK;
+  if (ptr) (void)hipHostFree(ptr);
+  ptr = nullptr;
+  cap = 0;
+  size_t want = bytes + bytes / 4 + 256;
+  if (hipHostMalloc(&ptr, want, hipHostMallocDefault) != hipSuccess) {
+    ptr = nullptr;
+    return FSE_ERR_DEVICE;
+  }
+  cap = want;
+  return FSE_OK;
+}
+
+void HostBuf::release() {
+  if (ptr) (void)hipHostFree(ptr);
+  ptr = nullptr;
+  cap = 0;
+}
+
+int validate_params(const fse_params* p) {
+  if (!p) return FSE_ERR_INVALID;
+  if (p->block_w < 1 || p->block_h < 1 || p->block_w > 64 || p->block_h > 64) return FSE_ERR_INVALID;
+  if (p->border_d < 0 || p->fft_w < 1 || p->fft_h < 1) return FSE_ERR_INVALID;
+  if (p->block_w + 2 * p->border_d > p->fft_w || p->block_h + 2 * p->border_d > p->fft_h)
+    return FSE_ERR_INVALID;
+  if (!(p->rho > 0.0 && p->rho <= 1.0)) return FSE_ERR_INVALID;
+  if (!(p->delta >= 0.0 && p->delta <= 1.0)) return FSE_ERR_INVALID;
+  if (!(p->gamma > 0.0 && p->gamma <= 1.0)) return FSE_ERR_INVALID;
+  if (p->iterations < 1 || p->iterations > FSE_MAX_ITERATIONS) return FSE_ERR_INVALID;
+  if (p->order != FSE_ORDER_OPTIMIZED && p->order != FSE_ORDER_LINESCAN) return FSE_ERR_INVALID;
+  if (p->precision != FSE_FP64 && p->precision != FSE_FP32) return FSE_ERR_INVALID;
+  if (p->grid_off_x < 0 || p->grid_off_x >= p->block_w || p->grid_off_y < 0 ||
+      p->grid_off_y >= p->block_h)
+    return FSE_ERR_INVALID;
+  if (!std::isfinite(p->empty_fill)) return FSE_ERR_INVALID;
+  if (p->device_mem_budget < 0 || p->max_inflight_frames < 0) return FSE_ERR_INVALID;
+  if (p->flags & ~(FSE_FLAG_DEVICE_PTRS)) return FSE_ERR_INVALID;
+  if (p->fft_w != kFft || p->fft_h != kFft) return FSE_ERR_UNSUPPORTED;
+  return FSE_OK;
+}
+
+int validate_frame(const fse_frame* f, bool device_ptrs) {
+  if (!f || !f->image || !f->lost || !f->out) return FSE_ERR_INVALID;
+  if (f->width <= 0 || f->height <= 0) return FSE_ERR_INVALID;
+  if (f->width > 65535 * 1 || f->height > 65535) return FSE_ERR_INVALID;
+  if (f->stride < f->width || f->lost_stride < f->width || f->out_stride < f->width)
+    return FSE_ERR_INVALID;
+  if (device_ptrs && f->trace) return FSE_ERR_INVALID;
+  if (f->trace && (f->trace->capacity < 0 ||
+                   (f->trace->capacity > 0 &&
+                    (!f->trace->block || !f->trace->wave || !f->trace->u || !f->trace->dc))))
+    return FSE_ERR_INVALID;
+  return FSE_OK;
+}
+
+static void make_tables(fse_plan_s* pl) {
+  const int M = pl->M, N = pl->N;
+  pl->radial.resize((size_t)M * N);
+  const double cm = 0.5 * (M - 1), cn = 0.5 * (N - 1);
+  for (int m = 0; m < M; ++m)
+    for (int n = 0; n < N; ++n) {
+      const double dm = m - cm, dn = n - cn;
+      pl->radial[(size_t)m * N + n] = std::pow(pl->p.rho, std::sqrt(dm * dm + dn * dn));
+    }
+  // cos/sin(2 pi t / 64); the second half mirrors the first exactly
+  pl->twid.assign(2 * kFft, 0.0);
+  for (int t = 0; t <= kFft / 2; ++t) {
+    const double ang = 2.0 * M_PI * t / kFft;
+    pl->twid[2 * t] = std::cos(ang);
+    pl->twid[2 * t + 1] = std::sin(ang);
+  }
+  pl->twid[2 * (kFft / 4)] = 0.0;
+  pl->twid[2 * (kFft / 2) + 1] = 0.0;
+  for (int t = kFft / 2 + 1; t < kFft; ++t) {
+    pl->twid[2 * t] = pl->twid[2 * (kFft - t)];
+    pl->twid[2 * t + 1] = -pl->twid[2 * (kFft - t) + 1];
+  }
+}
+
+int plan_device_init(fse_plan_s* pl) {
+  const size_t mn = (size_t)pl->M * pl->N;
+  if (pl->tbl_radial.reserve(mn * sizeof(double)) || pl->tbl_twid.reserve(2 * kFft * sizeof(double)) ||
+      pl->tbl_twid64.reserve(2 * kFft * sizeof(double)))
+    return FSE_ERR_DEVICE;
+  if (pl->p.precision == FSE_FP32) {
+    std::vector<float> r(mn), t(2 * kFft);
+    for (size_t i = 0; i < mn; ++i) r[i] = (float)pl->radial[i];
+    for (int i = 0; i < 2 * kFft; ++i) t[i] = (float)pl->twid[i];
+    if (hipMemcpy(pl->tbl_radial.ptr, r.data(), mn * sizeof(float), hipMemcpyHostToDevice) ||
+        hipMemcpy(pl->tbl_twid.ptr, t.data(), t.size() * sizeof(float), hipMemcpyHostToDevice))
+      return FSE_ERR_DEVICE;
+  } else {
+    if (hipMemcpy(pl->tbl_radial.ptr, pl->radial.data(), mn * sizeof(double), hipMemcpyHostToDevice) ||
+        hipMemcpy(pl->tbl_twid.ptr, pl->twid.data(), 2 * kFft * sizeof(double), hipMemcpyHostToDevice))
+      return FSE_ERR_DEVICE;
+  }
+  if (hipMemcpy(pl->tbl_twid64.ptr, pl->twid.data(), 2 * kFft * sizeof(double), hipMemcpyHostToDevice))
+    return FSE_ERR_DEVICE;
+  return FSE_OK;
+}
+
+// ------------------------------------------------------------ batch execution
+
+template <typename T>
+static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
+  const fse_params& p = pl->p;
+  const bool dev = (p.flags & FSE_FLAG_DEVICE_PTRS) != 0;
+  hipStream_t s = pl->stream;
+  const int Bh = p.block_h, Bw = p.block_w, gox = p.grid_off_x, goy = p.grid_off_y;
+  const int K = p.iterations;
+  auto chk = [&](hipError_t e) { return e == hipSuccess ? FSE_OK : FSE_ERR_DEVICE; };
+
+  // geometry and arena offsets (256-element aligned)
+  std::vector<FrameDesc> fd(n);
+  std::vector<int> hb(n), wb(n);
+  int64_t total = 0;
+  for (int f = 0; f < n; ++f) {
+    fd[f].off = total;
+    fd[f].H = frames[f].height;
+    fd[f].W = frames[f].width;
+    hb[f] = (frames[f].height + goy + Bh - 1) / Bh;
+    wb[f] = (frames[f].width + gox + Bw - 1) / Bw;
+    total += ((int64_t)frames[f].height * frames[f].width + 255) & ~255LL;
+  }
+  int rc = FSE_OK;
+  if ((rc = pl->work.reserve(total * sizeof(T))) || (rc = pl->state.reserve(total)) ||
+      (rc = pl->frames_dev.reserve(n * sizeof(FrameDesc))))
+    return rc;
+  if (!dev) {
+    if ((rc = pl->u8_img.reserve(total)) || (rc = pl->u8_lost.reserve(total)) ||
+        (rc = pl->u8_out.reserve(total)))
+      return rc;
+  }
+  T* work = (T*)pl->work.ptr;
+  uint8_t* state = (uint8_t*)pl->state.ptr;
+
+  // inputs -> working image and state map; per-frame block flags
+  std::vector<std::vector<uint8_t>> flags(n);
+  int64_t max_blocks = 0;
+  for (int f = 0; f < n; ++f) max_blocks = std::max<int64_t>(max_blocks, (int64_t)hb[f] * wb[f]);
+  if (dev && (rc = pl->flags_dev.reserve(max_blocks))) return rc;
+  for (int f = 0; f < n; ++f) {
+    const fse_frame& fr = frames[f];
+    const int H = fr.height, W = fr.width;
+    const uint8_t* dimg;
+    const uint8_t* dlost;
+    int istr, lstr;
+    if (dev) {
+      dimg = fr.image; dlost = fr.lost; istr = fr.stride; lstr = fr.lost_stride;
+    } else {
+      uint8_t* a = (uint8_t*)pl->u8_img.ptr + fd[f].off;
+      uint8_t* b = (uint8_t*)pl->u8_lost.ptr + fd[f].off;
+      if ((rc = chk(hipMemcpy2DAsync(a, W, fr.image, fr.stride, W, H, hipMemcpyHostToDevice, s))) ||
+          (rc = chk(hipMemcpy2DAsync(b, W, fr.lost, fr.lost_stride, W, H, hipMemcpyHostToDevice, s))))
+        return rc;
+      dimg = a; dlost = b; istr = W; lstr = W;
+    }
+    if ((rc = chk(launch_init<T>(dimg, istr, dlost, lstr, work + fd[f].off, state + fd[f].off, H, W, s))))
+      return rc;
+    flags[f].assign((size_t)hb[f] * wb[f], 0);
+    if (dev) {
+      if ((rc = chk(launch_block_flags(dlost, lstr, H, W, Bh, Bw, gox, goy, hb[f], wb[f],
+                                       (uint8_t*)pl->flags_dev.ptr, s))) ||
+          (rc = chk(hipMemcpyAsync(flags[f].data(), pl->flags_dev.ptr, flags[f].size(),
+                                   hipMemcpyDeviceToHost, s))) ||
+          (rc = chk(hipStreamSynchronize(s))))
+        return rc;
+    } else {
+      for (int y = 0; y < H; ++y) {
+        const uint8_t* row = fr.lost + (int64_t)y * fr.lost_stride;
+        const int bi = (y + goy) / Bh;
+        for (int x = 0; x < W; ++x)
+          if (row[x]) flags[f][(size_t)bi * wb[f] + (x + gox) / Bw] = 1;
+      }
+    }
+  }
+
+  // processing order per frame, merged by wave index
+  std::vector<std::vector<int32_t>> wave_of(n), seq(n);
+  int max_waves = 0;
+  for (int f = 0; f < n; ++f) {
+    wave_of[f].resize(flags[f].size());
+    int nw = schedule_blocks(hb[f], wb[f], flags[f].data(), p.order, wave_of[f].data(), &seq[f]);
+    max_waves = std::max(max_waves, nw);
+    if (frames[f].stats) {
+      fse_stats* st = frames[f].stats;
+      st->waves = nw;
+      st->lost_blocks = (int32_t)seq[f].size();
+      int best = 0, run = 0, prev = -1;
+      for (int32_t b : seq[f]) {
+        int w = wave_of[f][b];
+        run = (w == prev) ? run + 1 : 1;
+        prev = w;
+        best = std::max(best, run);
+      }
+      st->max_wave_blocks = best;
+      st->latency_ms = 0.0;
+    }
+  }
+  std::vector<int32_t> items;
+  std::vector<int64_t> wave_start(max_waves + 1, 0);
+  std::vector<size_t> pos(n, 0);
+  std::vector<std::pair<int, int32_t>> item_src;  // (frame, block) per item
+  for (int t = 0; t < max_waves; ++t) {
+    wave_start[t] = (int64_t)items.size() / 2;
+    for (int f = 0; f < n; ++f) {
+      while (pos[f] < seq[f].size() && wave_of[f][seq[f][pos[f]]] == t) {
+        const int32_t b = seq[f][pos[f]++];
+        items.push_back(f);
+        items.push_back(((b / wb[f]) << 16) | (b % wb[f]));
+        item_src.emplace_back(f, b);
+      }
+    }
+  }
+  wave_start[max_waves] = (int64_t)items.size() / 2;
+  const int64_t n_items = wave_start[max_waves];
+
+  const bool staged = p.border_d > std::min(Bh, Bw);
+  bool want_trace = false;
+  for (int f = 0; f < n; ++f) want_trace |= frames[f].trace != nullptr;
+  if ((rc = pl->items_dev.reserve(std::max<int64_t>(1, n_items) * 2 * sizeof(int32_t))))
+    return rc;
+  if (staged && (rc = pl->staging.reserve(std::max<int64_t>(1, n_items) * Bh * Bw * sizeof(T))))
+    return rc;
+  if (want_trace && ((rc = pl->trace_u.reserve(std::max<int64_t>(1, n_items) * K * sizeof(int32_t))) ||
+                     (rc = pl->trace_dc.reserve(std::max<int64_t>(1, n_items) * K * 2 * sizeof(T)))))
+    return rc;
+  if (n_items > 0 &&
+      (rc = chk(hipMemcpyAsync(pl->items_dev.ptr, items.data(), items.size() * sizeof(int32_t),
+                               hipMemcpyHostToDevice, s))))
+    return rc;
+  if ((rc = chk(hipMemcpyAsync(pl->frames_dev.ptr, fd.data(), n * sizeof(FrameDesc),
+                               hipMemcpyHostToDevice, s))))
+    return rc;
+
+  BlockArgs<T> a;
+  a.work = work;
+  a.state = state;
+  a.frames = (const FrameDesc*)pl->frames_dev.ptr;
+  a.radial = (const T*)pl->tbl_radial.ptr;
+  a.twid = (const T*)pl->tbl_twid.ptr;
+  a.twid64 = (const double*)pl->tbl_twid64.ptr;
+  a.M = pl->M;
+  a.N = pl->N;
+  a.Bh = Bh;
+  a.Bw = Bw;
+  a.d = p.border_d;
+  a.gox = gox;
+  a.goy = goy;
+  a.K = K;
+  a.delta = (T)p.delta;
+  a.gamma = (T)p.gamma;
+  a.zscale = (T)128.0;
+  a.empty_fill = p.empty_fill;
+  const size_t lds = (size_t)lds_bytes<T>(pl->M, pl->N, K);
+
+  while ((int)pl->events.size() < 2 * max_waves) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return FSE_ERR_DEVICE;
+    pl->events.push_back(e);
+  }
+  for (int t = 0; t < max_waves; ++t) {
+    const int64_t i0 = wave_start[t], cnt = wave_start[t + 1] - i0;
+    a.items = (const int32_t*)pl->items_dev.ptr + 2 * i0;
+    a.staging = staged ? (T*)pl->staging.ptr : nullptr;
+    a.trace_u = want_trace ? (int32_t*)pl->trace_u.ptr + i0 * K : nullptr;
+    a.trace_dc = want_trace ? (T*)pl->trace_dc.ptr + i0 * K * 2 : nullptr;
+    if ((rc = chk(hipEventRecord(pl->events[2 * t], s)))) return rc;
+    if ((rc = chk(launch_block<T>(a, (int)cnt, lds, s)))) return rc;
+    if ((rc = chk(hipEventRecord(pl->events[2 * t + 1], s)))) return rc;
+    if (staged && (rc = chk(launch_scatter<T>(work, state, a.frames, a.items, (int)cnt,
+                                              (const T*)pl->staging.ptr, Bh, Bw, gox, goy, s))))
+      return rc;
+  }
+
+  // outputs
+  for (int f = 0; f < n; ++f) {
+    const fse_frame& fr = frames[f];
+    const int H = fr.height, W = fr.width;
+    float* of32 = fr.out_f32;
+    double* of64 = fr.out_f64;
+    if (!dev) {
+      size_t need = (of32 ? (size_t)H * W * 4 : 0) + (of64 ? (size_t)H * W * 8 : 0);
+      if (need && (rc = pl->fout.reserve(need))) return rc;
+      of32 = fr.out_f32 ? (float*)pl->fout.ptr : nullptr;
+      of64 = fr.out_f64 ? (double*)((char*)pl->fout.ptr + (fr.out_f32 ? (size_t)H * W * 4 : 0)) : nullptr;
+      uint8_t* dout = (uint8_t*)pl->u8_out.ptr + fd[f].off;
+      if ((rc = chk(launch_finalize<T>((uint8_t*)pl->u8_img.ptr + fd[f].off, W, state + fd[f].off,
+                                       work + fd[f].off, dout, W, of32, of64, H, W, s))) ||
+          (rc = chk(hipMemcpy2DAsync(fr.out, fr.out_stride, dout, W, W, H, hipMemcpyDeviceToHost, s))))
+        return rc;
+      if (of32 && (rc = chk(hipMemcpyAsync(fr.out_f32, of32, (size_t)H * W * 4, hipMemcpyDeviceToHost, s))))
+        return rc;
+      if (of64 && (rc = chk(hipMemcpyAsync(fr.out_f64, of64, (size_t)H * W * 8, hipMemcpyDeviceToHost, s))))
+        return rc;
+      // the f32/f64 staging is reused per frame: finish this frame's copies
+      if ((of32 || of64) && (rc = chk(hipStreamSynchronize(s)))) return rc;
+    } else {
+      if ((rc = chk(launch_finalize<T>(fr.image, fr.stride, state + fd[f].off, work + fd[f].off,
+                                       fr.out, fr.out_stride, of32, of64, H, W, s))))
+        return rc;
+    }
+  }
+  if ((rc = chk(hipStreamSynchronize(s)))) return rc;
+
+  double kms = 0.0;
+  for (int t = 0; t < max_waves; ++t) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, pl->events[2 * t], pl->events[2 * t + 1]) == hipSuccess) kms += ms;
+  }
+  pl->last.kernel_ms = kms;
+  pl->last.launches = max_waves;
+  pl->last.blocks = n_items;
+
+  if (want_trace && n_items > 0) {
+    std::vector<int32_t> tu((size_t)n_items * K);
+    std::vector<T> tdc((size_t)n_items * K * 2);
+    if ((rc = chk(hipMemcpy(tu.data(), pl->trace_u.ptr, tu.size() * sizeof(int32_t), hipMemcpyDeviceToHost))) ||
+        (rc = chk(hipMemcpy(tdc.data(), pl->trace_dc.ptr, tdc.size() * sizeof(T), hipMemcpyDeviceToHost))))
+      return rc;
+    std::vector<int32_t> cnt(n, 0);
+    for (int64_t i = 0; i < n_items; ++i) {
+      const int f = item_src[i].first;
+      fse_trace* tr = frames[f].trace;
+      if (!tr) continue;
+      const int slot = cnt[f]++;
+      if (slot >= tr->capacity) continue;
+      const int32_t b = item_src[i].second;
+      tr->block[slot] = b;
+      tr->wave[slot] = wave_of[f][b];
+      for (int k = 0; k < K; ++k) {
+        tr->u[(size_t)slot * K + k] = tu[(size_t)i * K + k];
+        tr->dc[((size_t)slot * K + k) * 2] = (double)tdc[((size_t)i * K + k) * 2];
+        tr->dc[((size_t)slot * K + k) * 2 + 1] = (double)tdc[((size_t)i * K + k) * 2 + 1];
+      }
+    }
+    for (int f = 0; f < n; ++f)
+      if (frames[f].trace) frames[f].trace->count = (int32_t)seq[f].size();
+  } else {
+    for (int f = 0; f < n; ++f)
+      if (frames[f].trace) frames[f].trace->count = (int32_t)seq[f].size();
+  }
+  return FSE_OK;
+}
+
+int conceal_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
+  return pl->p.precision == FSE_FP64 ? run_batch<double>(pl, frames, n)
+                                     : run_batch<float>(pl, frames, n);
+}
+
+}  // namespace fse
+
+using namespace fse;
+
+extern "C" {
+
+int32_t fse_plan(const fse_params* p, void* hip_stream, fse_plan_t* out) {
+  if (!out) return FSE_ERR_INVALID;
+  *out = nullptr;
+  int rc = validate_params(p);
+  if (rc) return rc;
+  const int M = p->block_h + 2 * p->border_d, N = p->block_w + 2 * p->border_d;
+  const int K = p->iterations;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return FSE_ERR_DEVICE;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return FSE_ERR_DEVICE;
+  const int64_t need = p->precision == FSE_FP64 ? lds_bytes<double>(M, N, K) : lds_bytes<float>(M, N, K);
+  if (need > (int64_t)prop.sharedMemPerBlock) return FSE_ERR_UNSUPPORTED;
+  fse_plan_s* pl = new fse_plan_s();
+  pl->p = *p;
+  pl->M = M;
+  pl->N = N;
+  pl->device = dev;
+  if (hip_stream) {
+    pl->stream = (hipStream_t)hip_stream;
+    pl->own_stream = false;
+  } else {
+    if (hipStreamCreateWithFlags(&pl->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete pl;
+      return FSE_ERR_DEVICE;
+    }
+    pl->own_stream = true;
+  }
+  make_tables(pl);
+  rc = plan_device_init(pl);
+  if (rc) {
+    fse_plan_destroy(pl);
+    return rc;
+  }
+  rc = serving_init(pl);
+  if (rc) {
+    fse_plan_destroy(pl);
+    return rc;
+  }
+  *out = pl;
+  return FSE_OK;
+}
+
+int32_t fse_plan_destroy(fse_plan_t pl) {
+  if (!pl) return FSE_OK;
+  serving_shutdown(pl);
+  if (pl->stream) (void)hipStreamSynchronize(pl->stream);
+  for (hipEvent_t e : pl->events) (void)hipEventDestroy(e);
+  pl->events.clear();
+  DevBuf* bufs[] = {&pl->tbl_radial, &pl->tbl_twid, &pl->tbl_twid64, &pl->work, &pl->state,
+                    &pl->frames_dev, &pl->items_dev, &pl->u8_img, &pl->u8_lost, &pl->u8_out,
+                    &pl->fout, &pl->staging, &pl->trace_u, &pl->trace_dc, &pl->flags_dev};
+  for (DevBuf* b : bufs) b->release();
+  if (pl->own_stream && pl->stream) (void)hipStreamDestroy(pl->stream);
+  delete pl;
+  return FSE_OK;
+}
+
+int32_t fse_conceal_image(fse_plan_t pl, const fse_frame* frames, int32_t n) {
+  if (!pl || !frames || n < 1) return FSE_ERR_INVALID;
+  const bool dev = (pl->p.flags & FSE_FLAG_DEVICE_PTRS) != 0;
+  for (int f = 0; f < n; ++f) {
+    int rc = validate_frame(&frames[f], dev);
+    if (rc) return rc;
+  }
+  std::lock_guard<std::mutex> lk(pl->exec_mu);
+  if (pl->sticky) return pl->sticky;
+  if (hipSetDevice(pl->device) != hipSuccess) return FSE_ERR_DEVICE;
+  auto t0 = std::chrono::steady_clock::now();
+  int rc = conceal_batch(pl, frames, n);
+  auto t1 = std::chrono::steady_clock::now();
+  pl->last.total_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  if (rc == FSE_ERR_DEVICE) pl->sticky = rc;
+  return rc;
+}
+
+int32_t fse_schedule(int32_t hb, int32_t wb, const uint8_t* lost, int32_t order,
+                     int32_t* wave_of, int32_t* seq) {
+  if (hb < 0 || wb < 0 || (hb * (int64_t)wb > 0 && (!lost || !wave_of))) return FSE_ERR_INVALID;
+  if (order != FSE_ORDER_OPTIMIZED && order != FSE_ORDER_LINESCAN) return FSE_ERR_INVALID;
+  if (hb == 0 || wb == 0) return 0;
+  std::vector<int32_t> s;
+  int nw = schedule_blocks(hb, wb, lost, order, wave_of, seq ? &s : nullptr);
+  if (seq) std::copy(s.begin(), s.end(), seq);
+  return nw;
+}
+
+int32_t fse_last_call_stats(fse_plan_t pl, fse_call_stats* out) {
+  if (!pl || !out) return FSE_ERR_INVALID;
+  *out = pl->last;
+  return FSE_OK;
+}
+
+const char* fse_strerror(int32_t code) {
+  switch (code) {
+    case FSE_OK: return "ok";
+    case FSE_PENDING: return "pending";
+    case FSE_ERR_INVALID: return "invalid argument";
+    case FSE_ERR_UNSUPPORTED: return "unsupported by this build";
+    case FSE_ERR_NOMEM: return "does not fit the device memory budget";
+    case FSE_ERR_AGAIN: return "serving queue full, retry";
+    case FSE_ERR_DEVICE: return "HIP device error";
+    case FSE_ERR_TICKET: return "unknown ticket";
+    default: return "unknown error code";
+  }
+}
+
+}  // extern "C"

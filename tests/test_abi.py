@@ -1,0 +1,105 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+declared in include/fse.h, validates parameters before touching a device, and
+its host scheduler agrees with the oracle's independent one."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+from hypothesis import given, settings, strategies as st
+
+import oracle
+import paper_2207_00233_amd as fse
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(fse.LIB_PATH):
+        from paper_2207_00233_amd import build
+        build.build()
+    return fse.load()
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            names |= set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(fse_[a-z_0-9]+)\s*\(",
+                                    src, re.M))
+    return names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert {"fse_plan", "fse_conceal_image", "fse_submit", "fse_poll"} <= names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(fse.EXPORTED) == names
+
+
+def test_strerror(lib):
+    assert lib.fse_strerror(0) == b"ok"
+    assert b"invalid" in lib.fse_strerror(fse.FSE_ERR_INVALID)
+    assert lib.fse_strerror(12345) == b"unknown error code"
+
+
+@pytest.mark.parametrize("field,value", [
+    ("block_w", 0), ("block_h", 65), ("border_d", -1), ("border_d", 30),
+    ("rho", 0.0), ("rho", 1.5), ("delta", -0.1), ("gamma", 0.0), ("gamma", 1.2),
+    ("iterations", 0), ("iterations", 5000), ("order", 7), ("precision", 9),
+    ("grid_off_x", 16), ("grid_off_y", -1), ("flags", 1 << 8),
+    ("empty_fill", float("nan")), ("device_mem_budget", -5),
+])
+def test_plan_rejects_invalid_params(lib, field, value):
+    p = fse.Params(border_d=14)
+    setattr(p, field, value)
+    pc = p.c()
+    h = ctypes.c_void_p(1234)
+    assert lib.fse_plan(ctypes.byref(pc), None, ctypes.byref(h)) == fse.FSE_ERR_INVALID
+    assert h.value is None
+
+
+def test_plan_rejects_other_fft_sizes(lib):
+    p = fse.Params(border_d=4, fft_w=32, fft_h=32)
+    pc = p.c()
+    h = ctypes.c_void_p()
+    assert lib.fse_plan(ctypes.byref(pc), None, ctypes.byref(h)) == fse.FSE_ERR_UNSUPPORTED
+
+
+def test_null_arguments(lib):
+    assert lib.fse_plan(None, None, None) == fse.FSE_ERR_INVALID
+    assert lib.fse_conceal_image(None, None, 1) == fse.FSE_ERR_INVALID
+    assert lib.fse_submit(None, None, None) == fse.FSE_ERR_INVALID
+    assert lib.fse_poll(None, 1, 0) == fse.FSE_ERR_INVALID
+    assert lib.fse_plan_destroy(None) == fse.FSE_OK
+    assert lib.fse_last_call_stats(None, None) == fse.FSE_ERR_INVALID
+    assert lib.fse_schedule(2, 2, None, 0, None, None) == fse.FSE_ERR_INVALID
+    assert lib.fse_schedule(0, 5, None, 0, None, None) == 0
+
+
+@settings(max_examples=200, deadline=None)
+@given(st.integers(1, 14), st.integers(1, 14), st.integers(0, 2**31 - 1),
+       st.floats(0.0, 1.0), st.sampled_from([0, 1]))
+def test_host_scheduler_matches_oracle(lib, hb, wb, seed, p, order):
+    lost = (np.random.default_rng(seed).random((hb, wb)) < p).astype(np.uint8)
+    a = fse.fse_schedule(lost, order)
+    b = oracle.schedule(lost, order)
+    assert a[0] == b[0]
+    np.testing.assert_array_equal(a[1], b[1])
+    np.testing.assert_array_equal(a[2], b[2])
+
+
+def test_host_scheduler_large_grid(lib):
+    # 2160p grid with slice losses, against the oracle
+    from paper_2207_00233_amd import synth
+    rng = np.random.default_rng(1)
+    lost = synth.slice_loss(rng, 2160, 3840, 16, (0.1, 0.2))
+    grid = lost.reshape(135, 16, 240, 16).any(axis=(1, 3)).astype(np.uint8)
+    a = fse.fse_schedule(grid)
+    b = oracle.schedule(grid)
+    assert a[0] == b[0]
+    np.testing.assert_array_equal(a[1], b[1])
