@@ -19,6 +19,19 @@ struct FrameDesc {
   int32_t H, W;  // image size
 };
 
+// Per-frame input/output pointers of the batched init and finalize kernels.
+struct IoDesc {
+  const uint8_t* image;  // 8-bit input (device)
+  const uint8_t* lost;   // loss mask (device)
+  uint8_t* out;          // 8-bit output (device)
+  float* of32;           // nullable unquantized outputs (device, contiguous)
+  double* of64;
+  int64_t off;           // element offset in the work/state arenas
+  int64_t flag_off;      // offset of the frame's block flags
+  int32_t stride, lstride, ostride;
+  int32_t H, W, wb;
+};
+
 // Arguments of the fused per-block kernel.  T = float or double.
 template <typename T>
 struct BlockArgs {
@@ -42,14 +55,15 @@ template <typename T>
 inline int64_t lds_bytes(int M, int N, int K) {
   const int NP = N | 1;  // odd row pitch for the staged area
   int64_t stage = 2LL * M * NP * sizeof(T) + 2LL * M * kHalf * 2 * sizeof(T);
-  int64_t wreg = (int64_t)kFft * kFft * 2 * sizeof(T);
+  int64_t wreg = (int64_t)(kFft + kRowsPerWave - 1) * kFft * 2 * sizeof(T);
   int64_t region = stage > wreg ? stage : wreg;
   region = (region + 15) & ~15LL;
   int64_t hist = (int64_t)K * (2 * sizeof(T)) + (int64_t)K * sizeof(int32_t);
   hist = (hist + 15) & ~15LL;
-  int64_t tw = kFft * 2 * sizeof(double);
-  int64_t slots = 2 * kWaves * 4 * sizeof(double) + 4 * sizeof(double);
-  return region + hist + tw + slots;
+  int64_t tw = kFft * 2 * sizeof(double) + kFft * 2 * sizeof(T);
+  int64_t slots = 2 * kWaves * (3 * sizeof(T) + 4 + (sizeof(T) == 8 ? 4 : 0));
+  int64_t misc = 4 * sizeof(double);
+  return region + hist + tw + slots + misc;
 }
 
 }  // namespace fse

@@ -43,7 +43,7 @@ struct fse_plan_s {
   std::vector<double> twid;    // 64 x (cos, sin)(2 pi t / 64)
   fse::DevBuf tbl_radial, tbl_twid, tbl_twid64;
   fse::DevBuf work, state, frames_dev, items_dev, u8_img, u8_lost, u8_out, fout, staging,
-      trace_u, trace_dc, flags_dev;
+      trace_u, trace_dc, flags_dev, io_dev;
   std::vector<hipEvent_t> events;
   fse_call_stats last{};
   int sticky = 0;

@@ -55,6 +55,55 @@ __device__ __forceinline__ double read_lane<double>(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// One DPP step of a wavefront max: x = max(x, x moved by `ctrl`).  Lanes
+// outside row_mask keep their own value, so the step is idempotent there.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float dpp_max_step(float x) {
+  int y = __builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x), CTRL, ROWMASK, 0xF,
+                                      false);
+  return fmaxf(x, __int_as_float(y));
+}
+
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_max_step(double x) {
+  long long b = __double_as_longlong(x);
+  int lo = (int)(b & 0xffffffffLL), hi = (int)(b >> 32);
+  int ylo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWMASK, 0xF, false);
+  int yhi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWMASK, 0xF, false);
+  double y = __longlong_as_double(((long long)yhi << 32) | (unsigned int)ylo);
+  return fmax(x, y);
+}
+
+// Wavefront maximum (exact: max is order-free); returned uniform.
+template <typename T>
+__device__ __forceinline__ T wave_max(T x) {
+  x = dpp_max_step<0xB1, 0xF>(x);   // quad_perm [1,0,3,2]
+  x = dpp_max_step<0x4E, 0xF>(x);   // quad_perm [2,3,0,1]
+  x = dpp_max_step<0x124, 0xF>(x);  // row_ror:4
+  x = dpp_max_step<0x128, 0xF>(x);  // row_ror:8 -> every lane holds its row max
+  x = dpp_max_step<0x142, 0xA>(x);  // row_bcast:15 -> rows 1, 3
+  x = dpp_max_step<0x143, 0xC>(x);  // row_bcast:31 -> row 3 holds the wave max
+  return read_lane(x, 63);
+}
+
+template <typename T>
+__device__ __forceinline__ T max3(T a, T b, T c) {
+  return fmax(a, fmax(b, c));
+}
+template <>
+__device__ __forceinline__ float max3<float>(float a, float b, float c) {
+  return fmaxf(a, fmaxf(b, c));
+}
+
+// Result of one wavefront's argmax, exchanged through LDS.
+template <typename T>
+struct Slot {
+  T e, re, im;
+  int k;
+};
+
+constexpr int kWRows = kFft + kRowsPerWave - 1;  // rows 64.. repeat rows 0..14
+
 struct Lds {
   int64_t region, hist;
 };
@@ -63,7 +112,7 @@ template <typename T>
 __device__ __forceinline__ Lds lds_layout(int M, int N, int K) {
   const int NP = N | 1;
   int64_t stage = 2LL * M * NP * sizeof(T) + 2LL * M * kHalf * 2 * sizeof(T);
-  int64_t wreg = (int64_t)kFft * kFft * 2 * sizeof(T);
+  int64_t wreg = (int64_t)kWRows * kFft * 2 * sizeof(T);
   int64_t region = stage > wreg ? stage : wreg;
   region = (region + 15) & ~15LL;
   int64_t hist = (int64_t)K * (2 * sizeof(T)) + (int64_t)K * sizeof(int32_t);
@@ -84,12 +133,13 @@ __global__ __launch_bounds__(kThreads) void fse_block_kernel(BlockArgs<T> a) {
   T* ws = xs + M * NP;
   T* bx = ws + M * NP;
   T* bw = bx + M * kHalf * 2;
-  T* Wl = reinterpret_cast<T*>(smem);  // 64 x 64 complex, after phase C
+  T* Wl = reinterpret_cast<T*>(smem);  // kWRows x 64 complex, after phase C
   T* hdc = reinterpret_cast<T*>(smem + L.region);
   int* hu = reinterpret_cast<int*>(hdc + 2 * K);
-  double* tw = reinterpret_cast<double*>(smem + L.region + L.hist);  // 128
-  double* slots = tw + 2 * kFft;  // 2 x 4 x {e, k, re, im}
-  double* misc = slots + 2 * kWaves * 4;
+  double* tw = reinterpret_cast<double*>(smem + L.region + L.hist);  // 64 x (cos, sin)
+  T* twt = reinterpret_cast<T*>(tw + 2 * kFft);                      // same, in T
+  Slot<T>* slots = reinterpret_cast<Slot<T>*>(twt + 2 * kFft);       // 2 x 4
+  double* misc = reinterpret_cast<double*>(slots + 2 * kWaves);
 
   const int item = blockIdx.x;
   const int fr = a.items[2 * item];
@@ -102,7 +152,11 @@ __global__ __launch_bounds__(kThreads) void fse_block_kernel(BlockArgs<T> a) {
   const int by0 = bi * a.Bh - a.goy, bx0 = bj * a.Bw - a.gox;
   const int oy = by0 - a.d, ox = bx0 - a.d;
 
-  if (tid < 2 * kFft) tw[tid] = a.twid64[tid];
+  if (tid < 2 * kFft) {
+    const double v = a.twid64[tid];
+    tw[tid] = v;
+    twt[tid] = (T)v;
+  }
 
   // ---- A: gather, classify, weight (Eq. (2)) ----
   T wsum = T(0);
@@ -126,10 +180,6 @@ __global__ __launch_bounds__(kThreads) void fse_block_kernel(BlockArgs<T> a) {
   __syncthreads();
   const T W0 = ((T)misc[0] + (T)misc[1]) + ((T)misc[2] + (T)misc[3]);
 
-  // twiddles in the working precision (wave-uniform reads broadcast)
-  auto twc = [&](int t) { return (T)tw[2 * t]; };
-  auto tws = [&](int t) { return (T)tw[2 * t + 1]; };
-
   if (W0 > T(0)) {
     // ---- B: real row DFTs, columns k2 = wave + 4q (q = 0..8), k2 <= 32 ----
     {
@@ -141,13 +191,12 @@ __global__ __launch_bounds__(kThreads) void fse_block_kernel(BlockArgs<T> a) {
           const T xv = xs[lane * NP + n], wv = ws[lane * NP + n];
 #pragma unroll
           for (int q = 0; q < 9; ++q) {
-            const int k2 = wave + 4 * q;
-            const int t = (k2 * n) & (kFft - 1);
-            const T c = twc(t), s = tws(t);
-            axr[q] += xv * c;
-            axi[q] -= xv * s;
-            awr[q] += wv * c;
-            awi[q] -= wv * s;
+            const int t = ((wave + 4 * q) * n) & (kFft - 1);
+            const T c = twt[2 * t], s = twt[2 * t + 1];
+            axr[q] = fma(xv, c, axr[q]);
+            axi[q] = fma(-xv, s, axi[q]);
+            awr[q] = fma(wv, c, awr[q]);
+            awi[q] = fma(-wv, s, awi[q]);
           }
         }
 #pragma unroll
@@ -177,13 +226,13 @@ __global__ __launch_bounds__(kThreads) void fse_block_kernel(BlockArgs<T> a) {
       for (int m = 0; m < M; ++m) {
         const T xr = bx[(m * kHalf + c) * 2], xi = sg * bx[(m * kHalf + c) * 2 + 1];
         const T wr = bw[(m * kHalf + c) * 2], wi = sg * bw[(m * kHalf + c) * 2 + 1];
-        const T zr = xr - zs * wi, zi = xi + zs * wr;
+        const T zr = fma(-zs, wi, xr), zi = fma(zs, wr, xi);
 #pragma unroll
         for (int j = 0; j < kRowsPerWave; ++j) {
           const int t = ((kRowsPerWave * wave + j) * m) & (kFft - 1);
-          const T cc = twc(t), ss = tws(t);
-          rr[j] += zr * cc + zi * ss;
-          ri[j] += zi * cc - zr * ss;
+          const T cc = twt[2 * t], ss = twt[2 * t + 1];
+          rr[j] = fma(zr, cc, fma(zi, ss, rr[j]));
+          ri[j] = fma(zi, cc, fma(-zr, ss, ri[j]));
         }
       }
     }
@@ -214,85 +263,88 @@ __global__ __launch_bounds__(kThreads) void fse_block_kernel(BlockArgs<T> a) {
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < kRowsPerWave; ++j) {
-      T* p = Wl + ((kRowsPerWave * wave + j) * kFft + lane) * 2;
+      const int row = kRowsPerWave * wave + j;
+      T* p = Wl + (row * kFft + lane) * 2;
       p[0] = wvr[j];
       p[1] = wvi[j];
+      if (row < kWRows - kFft) {  // wrap-around copy: a wave's 16 rows never wrap
+        T* q = Wl + ((row + kFft) * kFft + lane) * 2;
+        q[0] = wvr[j];
+        q[1] = wvi[j];
+      }
     }
     __syncthreads();
 
     // ---- D: K greedy iterations ----
+    // Each iteration first applies the previous selection's update (a zero
+    // update in the first iteration), then selects u = argmax |R|^2 with ties
+    // to the smallest row-major index, and forms the coefficient increment.
     const T gs = a.gamma / W0;
     int u = 0;
     T dcr = T(0), dci = T(0);
     for (int it = 0; it < K; ++it) {
-      T be = T(-1);
-      int bjx = 0;
-      if (it > 0) {
-        const int u1 = u >> 6, u2 = u & (kFft - 1);
-        const int col = (lane - u2) & (kFft - 1);
-        const int b = uniform_int((kRowsPerWave * wave - u1) & (kFft - 1));
-        if (b <= kFft - kRowsPerWave) {
-          const T* wp = Wl + (b * kFft + col) * 2;
+      const int col = (lane - (u & (kFft - 1))) & (kFft - 1);
+      const int b = uniform_int((kRowsPerWave * wave - (u >> 6)) & (kFft - 1));
+      const T* wp = Wl + (b * kFft + col) * 2;
+      Vec16<T> e;
 #pragma unroll
-          for (int j = 0; j < kRowsPerWave; ++j) {
-            const T wr = wp[j * kFft * 2], wi = wp[j * kFft * 2 + 1];
-            rr[j] -= dcr * wr - dci * wi;
-            ri[j] -= dcr * wi + dci * wr;
-            const T e = rr[j] * rr[j] + ri[j] * ri[j];
-            if (e > be) { be = e; bjx = j; }
-          }
-        } else {
+      for (int j = 0; j < kRowsPerWave; ++j) {
+        const T wr = wp[j * kFft * 2], wi = wp[j * kFft * 2 + 1];
+        T r = rr[j], q = ri[j];
+        r = fma(-dcr, wr, r);
+        r = fma(dci, wi, r);
+        q = fma(-dcr, wi, q);
+        q = fma(-dci, wr, q);
+        rr[j] = r;
+        ri[j] = q;
+        e[j] = fma(r, r, q * q);
+      }
+      T lm = max3(e[0], e[1], e[2]);
+      lm = max3(lm, e[3], e[4]);
+      lm = max3(lm, e[5], e[6]);
+      lm = max3(lm, e[7], e[8]);
+      lm = max3(lm, e[9], e[10]);
+      lm = max3(lm, e[11], e[12]);
+      lm = max3(lm, e[13], e[14]);
+      lm = fmax(lm, e[15]);
+      const T wm = wave_max(lm);
+      // first (row, lane) holding the wave maximum
+      unsigned long long hit = 0;
+      int jw = 0;
 #pragma unroll
-          for (int j = 0; j < kRowsPerWave; ++j) {
-            const T* wp = Wl + ((((b + j) & (kFft - 1)) * kFft) + col) * 2;
-            const T wr = wp[0], wi = wp[1];
-            rr[j] -= dcr * wr - dci * wi;
-            ri[j] -= dcr * wi + dci * wr;
-            const T e = rr[j] * rr[j] + ri[j] * ri[j];
-            if (e > be) { be = e; bjx = j; }
-          }
-        }
-      } else {
-#pragma unroll
-        for (int j = 0; j < kRowsPerWave; ++j) {
-          const T e = rr[j] * rr[j] + ri[j] * ri[j];
-          if (e > be) { be = e; bjx = j; }
+      for (int j = kRowsPerWave - 1; j >= 0; --j) {
+        const unsigned long long mj = __ballot(e[j] == wm);
+        if (mj) {
+          hit = mj;
+          jw = j;
         }
       }
-      // wavefront argmax; ties go to the smallest row-major index
-      int kk = ((kRowsPerWave * wave + bjx) << 6) | lane;
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) {
-        const T oe = __shfl_xor(be, off);
-        const int ok = __shfl_xor(kk, off);
-        if (oe > be || (oe == be && ok < kk)) { be = oe; kk = ok; }
-      }
-      kk = uniform_int(kk);
-      const int jw = (kk >> 6) & (kRowsPerWave - 1), lw = kk & (kFft - 1);
+      jw = uniform_int(jw);
+      const int lw = uniform_int(__builtin_ctzll(hit));
+      // the register-indexed moves must run on every lane before the
+      // cross-lane read, so they stay outside the lane-0 branch
       const T sr = read_lane((T)rr[jw], lw);
       const T si = read_lane((T)ri[jw], lw);
-      double* sl = slots + (it & 1) * kWaves * 4;
+      Slot<T>* sl = slots + (it & 1) * kWaves;
       if (lane == 0) {
-        sl[wave * 4 + 0] = (double)be;
-        sl[wave * 4 + 1] = (double)kk;
-        sl[wave * 4 + 2] = (double)sr;
-        sl[wave * 4 + 3] = (double)si;
+        Slot<T> v;
+        v.e = wm;
+        v.re = sr;
+        v.im = si;
+        v.k = ((kRowsPerWave * wave + jw) << 6) | lw;
+        sl[wave] = v;
       }
       __syncthreads();
-      double ge = sl[0];
-      int gk = (int)sl[1];
-      double gr = sl[2], gi = sl[3];
+      // waves cover increasing k, so a strict > keeps the smallest k on ties
+      Slot<T> best = sl[0];
 #pragma unroll
       for (int q = 1; q < kWaves; ++q) {
-        const double e = sl[q * 4];
-        const int k = (int)sl[q * 4 + 1];
-        if (e > ge || (e == ge && k < gk)) {
-          ge = e; gk = k; gr = sl[q * 4 + 2]; gi = sl[q * 4 + 3];
-        }
+        const Slot<T> c = sl[q];
+        if (c.e > best.e) best = c;
       }
-      u = gk;
-      dcr = gs * (T)gr;
-      dci = gs * (T)gi;
+      u = uniform_int(best.k);
+      dcr = gs * best.re;
+      dci = gs * best.im;
       if (tid == 0) {
         hu[it] = u;
         hdc[2 * it] = dcr;
@@ -320,7 +372,8 @@ __global__ __launch_bounds__(kThreads) void fse_block_kernel(BlockArgs<T> a) {
       for (int i = 0; i < K; ++i) {
         const int uu = hu[i];
         const int t = ((uu >> 6) * m + (uu & (kFft - 1)) * n) & (kFft - 1);
-        acc += (double)hdc[2 * i] * tw[2 * t] - (double)hdc[2 * i + 1] * tw[2 * t + 1];
+        acc = fma((double)hdc[2 * i], tw[2 * t], acc);
+        acc = fma(-(double)hdc[2 * i + 1], tw[2 * t + 1], acc);
       }
     }
     if (a.staging) {
@@ -361,61 +414,44 @@ __global__ void fse_scatter_kernel(T* work, uint8_t* state, const FrameDesc* fra
   }
 }
 
-// Working image and state map of one frame from the 8-bit input.
+// Working image and state map of every frame from its 8-bit input, and the
+// flag of every block that holds a lost sample.  blockIdx.y = frame.
 template <typename T>
-__global__ void fse_init_kernel(const uint8_t* image, int stride, const uint8_t* lost,
-                                int lstride, T* work, uint8_t* state, int H, int W) {
-  const int64_t n = (int64_t)H * W;
+__global__ void fse_init_kernel(const IoDesc* io, T* work, uint8_t* state, uint8_t* flags,
+                                int Bh, int Bw, int gox, int goy) {
+  const IoDesc d = io[blockIdx.y];
+  const int64_t n = (int64_t)d.H * d.W;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const int y = (int)(i / W), x = (int)(i - (int64_t)y * W);
-    const bool l = lost[(int64_t)y * lstride + x] != 0;
-    work[i] = l ? T(0) : (T)image[(int64_t)y * stride + x];
-    state[i] = l ? kPending : kKnown;
+    const int y = (int)(i / d.W), x = (int)(i - (int64_t)y * d.W);
+    const bool l = d.lost[(int64_t)y * d.lstride + x] != 0;
+    work[d.off + i] = l ? T(0) : (T)d.image[(int64_t)y * d.stride + x];
+    state[d.off + i] = l ? kPending : kKnown;
+    if (l) flags[d.flag_off + (int64_t)((y + goy) / Bh) * d.wb + (x + gox) / Bw] = 1;
   }
 }
 
-// Blocks holding at least one lost sample.
-__global__ void fse_block_flags_kernel(const uint8_t* lost, int lstride, int H, int W, int Bh,
-                                       int Bw, int gox, int goy, int wb, int nblocks,
-                                       uint8_t* flags) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nblocks) return;
-  const int bi = b / wb, bj = b - bi * wb;
-  const int y0 = bi * Bh - goy, x0 = bj * Bw - gox;
-  uint8_t f = 0;
-  for (int dy = 0; dy < Bh && !f; ++dy) {
-    const int y = y0 + dy;
-    if (y < 0 || y >= H) continue;
-    for (int dx = 0; dx < Bw; ++dx) {
-      const int x = x0 + dx;
-      if (x >= 0 && x < W && lost[(int64_t)y * lstride + x]) { f = 1; break; }
-    }
-  }
-  flags[b] = f;
-}
-
-// Output: known samples copied, lost samples rounded half-to-even and clamped.
+// Output of every frame: known samples copied, lost samples rounded
+// half-to-even and clamped to [0, 255].  blockIdx.y = frame.
 template <typename T>
-__global__ void fse_finalize_kernel(const uint8_t* image, int stride, const uint8_t* state,
-                                    const T* work, uint8_t* out, int ostride, float* of32,
-                                    double* of64, int H, int W) {
-  const int64_t n = (int64_t)H * W;
+__global__ void fse_finalize_kernel(const IoDesc* io, const uint8_t* state, const T* work) {
+  const IoDesc d = io[blockIdx.y];
+  const int64_t n = (int64_t)d.H * d.W;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const int y = (int)(i / W), x = (int)(i - (int64_t)y * W);
-    const T v = work[i];
+    const int y = (int)(i / d.W), x = (int)(i - (int64_t)y * d.W);
+    const T v = work[d.off + i];
     uint8_t o;
-    if (state[i] == kKnown) {
-      o = image[(int64_t)y * stride + x];
+    if (state[d.off + i] == kKnown) {
+      o = d.image[(int64_t)y * d.stride + x];
     } else {
       T r = rint(v);
       r = r < T(0) ? T(0) : (r > T(255) ? T(255) : r);
       o = (uint8_t)r;
     }
-    out[(int64_t)y * ostride + x] = o;
-    if (of32) of32[i] = (float)v;
-    if (of64) of64[i] = (double)v;
+    d.out[(int64_t)y * d.ostride + x] = o;
+    if (d.of32) d.of32[i] = (float)v;
+    if (d.of64) d.of64[i] = (double)v;
   }
 }
 
@@ -447,32 +483,24 @@ hipError_t launch_scatter(T* work, uint8_t* state, const FrameDesc* frames, cons
 
 static int grid_for(int64_t n) {
   int64_t g = (n + 255) / 256;
-  if (g > 65536) g = 65536;
+  if (g > 2048) g = 2048;
   return (int)(g < 1 ? 1 : g);
 }
 
 template <typename T>
-hipError_t launch_init(const uint8_t* image, int stride, const uint8_t* lost, int lstride,
-                       T* work, uint8_t* state, int H, int W, hipStream_t s) {
-  hipLaunchKernelGGL(fse_init_kernel<T>, dim3(grid_for((int64_t)H * W)), dim3(256), 0, s, image,
-                     stride, lost, lstride, work, state, H, W);
-  return hipGetLastError();
-}
-
-hipError_t launch_block_flags(const uint8_t* lost, int lstride, int H, int W, int Bh, int Bw,
-                              int gox, int goy, int hb, int wb, uint8_t* flags, hipStream_t s) {
-  const int nb = hb * wb;
-  hipLaunchKernelGGL(fse_block_flags_kernel, dim3((nb + 255) / 256), dim3(256), 0, s, lost,
-                     lstride, H, W, Bh, Bw, gox, goy, wb, nb, flags);
+hipError_t launch_init(const IoDesc* io, int nframes, int64_t max_pixels, T* work,
+                       uint8_t* state, uint8_t* flags, int Bh, int Bw, int gox, int goy,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(fse_init_kernel<T>, dim3(grid_for(max_pixels), nframes), dim3(256), 0, s,
+                     io, work, state, flags, Bh, Bw, gox, goy);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_finalize(const uint8_t* image, int stride, const uint8_t* state,
-                           const T* work, uint8_t* out, int ostride, float* of32, double* of64,
-                           int H, int W, hipStream_t s) {
-  hipLaunchKernelGGL(fse_finalize_kernel<T>, dim3(grid_for((int64_t)H * W)), dim3(256), 0, s,
-                     image, stride, state, work, out, ostride, of32, of64, H, W);
+hipError_t launch_finalize(const IoDesc* io, int nframes, int64_t max_pixels,
+                           const uint8_t* state, const T* work, hipStream_t s) {
+  hipLaunchKernelGGL(fse_finalize_kernel<T>, dim3(grid_for(max_pixels), nframes), dim3(256), 0,
+                     s, io, state, work);
   return hipGetLastError();
 }
 
@@ -482,14 +510,13 @@ template hipError_t launch_scatter<float>(float*, uint8_t*, const FrameDesc*, co
                                           const float*, int, int, int, int, hipStream_t);
 template hipError_t launch_scatter<double>(double*, uint8_t*, const FrameDesc*, const int32_t*,
                                            int, const double*, int, int, int, int, hipStream_t);
-template hipError_t launch_init<float>(const uint8_t*, int, const uint8_t*, int, float*, uint8_t*,
-                                       int, int, hipStream_t);
-template hipError_t launch_init<double>(const uint8_t*, int, const uint8_t*, int, double*,
-                                        uint8_t*, int, int, hipStream_t);
-template hipError_t launch_finalize<float>(const uint8_t*, int, const uint8_t*, const float*,
-                                           uint8_t*, int, float*, double*, int, int, hipStream_t);
-template hipError_t launch_finalize<double>(const uint8_t*, int, const uint8_t*, const double*,
-                                            uint8_t*, int, float*, double*, int, int,
-                                            hipStream_t);
+template hipError_t launch_init<float>(const IoDesc*, int, int64_t, float*, uint8_t*, uint8_t*,
+                                       int, int, int, int, hipStream_t);
+template hipError_t launch_init<double>(const IoDesc*, int, int64_t, double*, uint8_t*, uint8_t*,
+                                        int, int, int, int, hipStream_t);
+template hipError_t launch_finalize<float>(const IoDesc*, int, int64_t, const uint8_t*,
+                                           const float*, hipStream_t);
+template hipError_t launch_finalize<double>(const IoDesc*, int, int64_t, const uint8_t*,
+                                            const double*, hipStream_t);
 
 }  // namespace fse

@@ -30,14 +30,12 @@ hipError_t launch_scatter(T* work, uint8_t* state, const FrameDesc* frames, cons
                           int n_items, const T* staging, int Bh, int Bw, int gox, int goy,
                           hipStream_t s);
 template <typename T>
-hipError_t launch_init(const uint8_t* image, int stride, const uint8_t* lost, int lstride,
-                       T* work, uint8_t* state, int H, int W, hipStream_t s);
-hipError_t launch_block_flags(const uint8_t* lost, int lstride, int H, int W, int Bh, int Bw,
-                              int gox, int goy, int hb, int wb, uint8_t* flags, hipStream_t s);
+hipError_t launch_init(const IoDesc* io, int nframes, int64_t max_pixels, T* work,
+                       uint8_t* state, uint8_t* flags, int Bh, int Bw, int gox, int goy,
+                       hipStream_t s);
 template <typename T>
-hipError_t launch_finalize(const uint8_t* image, int stride, const uint8_t* state,
-                           const T* work, uint8_t* out, int ostride, float* of32, double* of64,
-                           int H, int W, hipStream_t s);
+hipError_t launch_finalize(const IoDesc* io, int nframes, int64_t max_pixels,
+                           const uint8_t* state, const T* work, hipStream_t s);
 
 int DevBuf::reserve(size_t bytes) {
   if (bytes <= cap) return FSE_OK;
@@ -185,64 +183,83 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
     total += ((int64_t)frames[f].height * frames[f].width + 255) & ~255LL;
   }
   int rc = FSE_OK;
+  // per-frame I/O descriptors; block flags of all frames in one array
+  std::vector<IoDesc> io(n);
+  std::vector<int64_t> fout_off(n, -1);
+  int64_t flag_total = 0, max_pixels = 0, fout_bytes = 0;
+  for (int f = 0; f < n; ++f) {
+    const fse_frame& fr = frames[f];
+    const int64_t px = (int64_t)fr.height * fr.width;
+    io[f].off = fd[f].off;
+    io[f].flag_off = flag_total;
+    io[f].H = fr.height;
+    io[f].W = fr.width;
+    io[f].wb = wb[f];
+    flag_total += (int64_t)hb[f] * wb[f];
+    max_pixels = std::max(max_pixels, px);
+    if (!dev && (fr.out_f32 || fr.out_f64)) {
+      fout_off[f] = fout_bytes;
+      fout_bytes += ((fr.out_f32 ? px * 4 : 0) + (fr.out_f64 ? px * 8 : 0) + 255) & ~255LL;
+    }
+  }
   if ((rc = pl->work.reserve(total * sizeof(T))) || (rc = pl->state.reserve(total)) ||
-      (rc = pl->frames_dev.reserve(n * sizeof(FrameDesc))))
+      (rc = pl->frames_dev.reserve(n * sizeof(FrameDesc))) ||
+      (rc = pl->io_dev.reserve(n * sizeof(IoDesc))) || (rc = pl->flags_dev.reserve(flag_total)))
     return rc;
   if (!dev) {
     if ((rc = pl->u8_img.reserve(total)) || (rc = pl->u8_lost.reserve(total)) ||
-        (rc = pl->u8_out.reserve(total)))
+        (rc = pl->u8_out.reserve(total)) || (fout_bytes && (rc = pl->fout.reserve(fout_bytes))))
       return rc;
   }
   T* work = (T*)pl->work.ptr;
   uint8_t* state = (uint8_t*)pl->state.ptr;
-
-  // inputs -> working image and state map; per-frame block flags
-  std::vector<std::vector<uint8_t>> flags(n);
-  int64_t max_blocks = 0;
-  for (int f = 0; f < n; ++f) max_blocks = std::max<int64_t>(max_blocks, (int64_t)hb[f] * wb[f]);
-  if (dev && (rc = pl->flags_dev.reserve(max_blocks))) return rc;
   for (int f = 0; f < n; ++f) {
     const fse_frame& fr = frames[f];
     const int H = fr.height, W = fr.width;
-    const uint8_t* dimg;
-    const uint8_t* dlost;
-    int istr, lstr;
     if (dev) {
-      dimg = fr.image; dlost = fr.lost; istr = fr.stride; lstr = fr.lost_stride;
+      io[f].image = fr.image;
+      io[f].lost = fr.lost;
+      io[f].out = fr.out;
+      io[f].stride = fr.stride;
+      io[f].lstride = fr.lost_stride;
+      io[f].ostride = fr.out_stride;
+      io[f].of32 = fr.out_f32;
+      io[f].of64 = fr.out_f64;
     } else {
       uint8_t* a = (uint8_t*)pl->u8_img.ptr + fd[f].off;
       uint8_t* b = (uint8_t*)pl->u8_lost.ptr + fd[f].off;
       if ((rc = chk(hipMemcpy2DAsync(a, W, fr.image, fr.stride, W, H, hipMemcpyHostToDevice, s))) ||
           (rc = chk(hipMemcpy2DAsync(b, W, fr.lost, fr.lost_stride, W, H, hipMemcpyHostToDevice, s))))
         return rc;
-      dimg = a; dlost = b; istr = W; lstr = W;
-    }
-    if ((rc = chk(launch_init<T>(dimg, istr, dlost, lstr, work + fd[f].off, state + fd[f].off, H, W, s))))
-      return rc;
-    flags[f].assign((size_t)hb[f] * wb[f], 0);
-    if (dev) {
-      if ((rc = chk(launch_block_flags(dlost, lstr, H, W, Bh, Bw, gox, goy, hb[f], wb[f],
-                                       (uint8_t*)pl->flags_dev.ptr, s))) ||
-          (rc = chk(hipMemcpyAsync(flags[f].data(), pl->flags_dev.ptr, flags[f].size(),
-                                   hipMemcpyDeviceToHost, s))) ||
-          (rc = chk(hipStreamSynchronize(s))))
-        return rc;
-    } else {
-      for (int y = 0; y < H; ++y) {
-        const uint8_t* row = fr.lost + (int64_t)y * fr.lost_stride;
-        const int bi = (y + goy) / Bh;
-        for (int x = 0; x < W; ++x)
-          if (row[x]) flags[f][(size_t)bi * wb[f] + (x + gox) / Bw] = 1;
-      }
+      io[f].image = a;
+      io[f].lost = b;
+      io[f].out = (uint8_t*)pl->u8_out.ptr + fd[f].off;
+      io[f].stride = io[f].lstride = io[f].ostride = W;
+      char* fo = fout_off[f] >= 0 ? (char*)pl->fout.ptr + fout_off[f] : nullptr;
+      io[f].of32 = fr.out_f32 ? (float*)fo : nullptr;
+      io[f].of64 = fr.out_f64 ? (double*)(fo + (fr.out_f32 ? (size_t)H * W * 4 : 0)) : nullptr;
     }
   }
+  if ((rc = chk(hipMemcpyAsync(pl->io_dev.ptr, io.data(), n * sizeof(IoDesc),
+                               hipMemcpyHostToDevice, s))) ||
+      (rc = chk(hipMemsetAsync(pl->flags_dev.ptr, 0, flag_total, s))) ||
+      (rc = chk(launch_init<T>((const IoDesc*)pl->io_dev.ptr, n, max_pixels, work, state,
+                               (uint8_t*)pl->flags_dev.ptr, Bh, Bw, gox, goy, s))))
+    return rc;
+  std::vector<uint8_t> allflags(flag_total);
+  if ((rc = chk(hipMemcpyAsync(allflags.data(), pl->flags_dev.ptr, flag_total,
+                               hipMemcpyDeviceToHost, s))) ||
+      (rc = chk(hipStreamSynchronize(s))))
+    return rc;
+  std::vector<const uint8_t*> flags(n);
+  for (int f = 0; f < n; ++f) flags[f] = allflags.data() + io[f].flag_off;
 
   // processing order per frame, merged by wave index
   std::vector<std::vector<int32_t>> wave_of(n), seq(n);
   int max_waves = 0;
   for (int f = 0; f < n; ++f) {
-    wave_of[f].resize(flags[f].size());
-    int nw = schedule_blocks(hb[f], wb[f], flags[f].data(), p.order, wave_of[f].data(), &seq[f]);
+    wave_of[f].resize((size_t)hb[f] * wb[f]);
+    int nw = schedule_blocks(hb[f], wb[f], flags[f], p.order, wave_of[f].data(), &seq[f]);
     max_waves = std::max(max_waves, nw);
     if (frames[f].stats) {
       fse_stats* st = frames[f].stats;
@@ -336,30 +353,20 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
   }
 
   // outputs
-  for (int f = 0; f < n; ++f) {
-    const fse_frame& fr = frames[f];
-    const int H = fr.height, W = fr.width;
-    float* of32 = fr.out_f32;
-    double* of64 = fr.out_f64;
-    if (!dev) {
-      size_t need = (of32 ? (size_t)H * W * 4 : 0) + (of64 ? (size_t)H * W * 8 : 0);
-      if (need && (rc = pl->fout.reserve(need))) return rc;
-      of32 = fr.out_f32 ? (float*)pl->fout.ptr : nullptr;
-      of64 = fr.out_f64 ? (double*)((char*)pl->fout.ptr + (fr.out_f32 ? (size_t)H * W * 4 : 0)) : nullptr;
-      uint8_t* dout = (uint8_t*)pl->u8_out.ptr + fd[f].off;
-      if ((rc = chk(launch_finalize<T>((uint8_t*)pl->u8_img.ptr + fd[f].off, W, state + fd[f].off,
-                                       work + fd[f].off, dout, W, of32, of64, H, W, s))) ||
-          (rc = chk(hipMemcpy2DAsync(fr.out, fr.out_stride, dout, W, W, H, hipMemcpyDeviceToHost, s))))
+  if ((rc = chk(launch_finalize<T>((const IoDesc*)pl->io_dev.ptr, n, max_pixels, state, work, s))))
+    return rc;
+  if (!dev) {
+    for (int f = 0; f < n; ++f) {
+      const fse_frame& fr = frames[f];
+      const int H = fr.height, W = fr.width;
+      if ((rc = chk(hipMemcpy2DAsync(fr.out, fr.out_stride, io[f].out, W, W, H,
+                                     hipMemcpyDeviceToHost, s))))
         return rc;
-      if (of32 && (rc = chk(hipMemcpyAsync(fr.out_f32, of32, (size_t)H * W * 4, hipMemcpyDeviceToHost, s))))
+      if (fr.out_f32 && (rc = chk(hipMemcpyAsync(fr.out_f32, io[f].of32, (size_t)H * W * 4,
+                                                 hipMemcpyDeviceToHost, s))))
         return rc;
-      if (of64 && (rc = chk(hipMemcpyAsync(fr.out_f64, of64, (size_t)H * W * 8, hipMemcpyDeviceToHost, s))))
-        return rc;
-      // the f32/f64 staging is reused per frame: finish this frame's copies
-      if ((of32 || of64) && (rc = chk(hipStreamSynchronize(s)))) return rc;
-    } else {
-      if ((rc = chk(launch_finalize<T>(fr.image, fr.stride, state + fd[f].off, work + fd[f].off,
-                                       fr.out, fr.out_stride, of32, of64, H, W, s))))
+      if (fr.out_f64 && (rc = chk(hipMemcpyAsync(fr.out_f64, io[f].of64, (size_t)H * W * 8,
+                                                 hipMemcpyDeviceToHost, s))))
         return rc;
     }
   }
@@ -467,7 +474,8 @@ int32_t fse_plan_destroy(fse_plan_t pl) {
   pl->events.clear();
   DevBuf* bufs[] = {&pl->tbl_radial, &pl->tbl_twid, &pl->tbl_twid64, &pl->work, &pl->state,
                     &pl->frames_dev, &pl->items_dev, &pl->u8_img, &pl->u8_lost, &pl->u8_out,
-                    &pl->fout, &pl->staging, &pl->trace_u, &pl->trace_dc, &pl->flags_dev};
+                    &pl->fout, &pl->staging, &pl->trace_u, &pl->trace_dc, &pl->flags_dev,
+                    &pl->io_dev};
   for (DevBuf* b : bufs) b->release();
   if (pl->own_stream && pl->stream) (void)hipStreamDestroy(pl->stream);
   delete pl;
