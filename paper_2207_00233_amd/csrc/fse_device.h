@@ -6,9 +6,6 @@
 namespace fse {
 
 constexpr int kFft = 64;          // basis grid edge (64 x 64 DFT basis)
-constexpr int kThreads = 256;     // one workgroup = 4 wavefronts
-constexpr int kWaves = 4;
-constexpr int kRowsPerWave = kFft / kWaves;  // 16 spectrum rows per wave
 constexpr int kHalf = kFft / 2 + 1;          // 33 columns of a real row DFT
 
 // Per-sample state in the device state map.
@@ -50,20 +47,45 @@ struct BlockArgs {
   double empty_fill;
 };
 
-// Bytes of dynamic LDS the fused kernel needs.
+// Byte offsets of the dynamic LDS regions of the fused block kernel with
+// `waves` wavefronts per workgroup (rows = 64 / waves spectrum rows each).
+struct LdsLayout {
+  int64_t bx, bw;    // phase B: row DFTs of x and w (M x 33 complex each)
+  int64_t hist_dc;   // K complex coefficient increments
+  int64_t hist_u;    // K selected indices
+  int64_t tw64;      // 64 x (cos, sin) in double
+  int64_t twt;       // the same in T
+  int64_t slots;     // 2 x waves argmax slots of 32 bytes
+  int64_t misc;      // 32 bytes
+  int64_t total;
+};
+
+__host__ __device__ inline int64_t align16(int64_t v) { return (v + 15) & ~15LL; }
+
+__host__ __device__ inline LdsLayout lds_layout(int M, int N, int K, int waves, int tsize) {
+  LdsLayout L;
+  const int NP = N | 1;  // odd row pitch of the staged area
+  const int rows = kFft / waves;
+  const int64_t stage_xw = 2LL * M * NP * tsize;
+  L.bx = stage_xw;
+  L.bw = L.bx + (int64_t)M * kHalf * 2 * tsize;
+  const int64_t stage = L.bw + (int64_t)M * kHalf * 2 * tsize;
+  // the W spectrum with rows - 1 wrap-around rows (rows 64.. repeat 0..)
+  const int64_t wreg = (int64_t)(kFft + rows - 1) * kFft * 2 * tsize;
+  const int64_t region = align16(stage > wreg ? stage : wreg);
+  L.hist_dc = region;
+  L.hist_u = L.hist_dc + (int64_t)K * 2 * tsize;
+  L.tw64 = align16(L.hist_u + (int64_t)K * 4);
+  L.twt = L.tw64 + kFft * 2 * 8;
+  L.slots = align16(L.twt + kFft * 2 * tsize);
+  L.misc = L.slots + 2LL * waves * 32;
+  L.total = L.misc + 32;
+  return L;
+}
+
 template <typename T>
-inline int64_t lds_bytes(int M, int N, int K) {
-  const int NP = N | 1;  // odd row pitch for the staged area
-  int64_t stage = 2LL * M * NP * sizeof(T) + 2LL * M * kHalf * 2 * sizeof(T);
-  int64_t wreg = (int64_t)(kFft + kRowsPerWave - 1) * kFft * 2 * sizeof(T);
-  int64_t region = stage > wreg ? stage : wreg;
-  region = (region + 15) & ~15LL;
-  int64_t hist = (int64_t)K * (2 * sizeof(T)) + (int64_t)K * sizeof(int32_t);
-  hist = (hist + 15) & ~15LL;
-  int64_t tw = kFft * 2 * sizeof(double) + kFft * 2 * sizeof(T);
-  int64_t slots = 2 * kWaves * (3 * sizeof(T) + 4 + (sizeof(T) == 8 ? 4 : 0));
-  int64_t misc = 4 * sizeof(double);
-  return region + hist + tw + slots + misc;
+inline int64_t lds_bytes(int M, int N, int K, int waves) {
+  return lds_layout(M, N, K, waves, (int)sizeof(T)).total;
 }
 
 }  // namespace fse

@@ -45,6 +45,12 @@ struct fse_plan_s {
   fse::DevBuf work, state, frames_dev, items_dev, u8_img, u8_lost, u8_out, fout, staging,
       trace_u, trace_dc, flags_dev, io_dev;
   std::vector<hipEvent_t> events;
+  int wide_threshold = 256;  // waves with at most this many blocks use 16 wavefronts per block
+  bool stagger = true;       // staggered frame starts inside a batch
+  // launch cost model used to stagger frames: max(latency, blocks / rate),
+  // [0] = FP64, [1] = FP32; measured on MI355X for 16x16 blocks, d = 14, K = 200
+  double model_latency_us[2] = {260.0, 150.0};
+  double model_rate[2] = {1.0, 3.1};  // blocks per microsecond
   fse_call_stats last{};
   int sticky = 0;
   std::mutex exec_mu;  // one synchronous call at a time

@@ -1,6 +1,6 @@
 // fse_kernels.hip -- HIP kernels (gfx950) of Frequency Selective Extrapolation.
 //
-// One workgroup (256 threads, 4 wavefronts) extrapolates one lost block:
+// One workgroup of WAVES wavefronts extrapolates one lost block:
 //   A  gather the extrapolation area L (block + frame of d samples, paper
 //      Section 2) from the working image, classify every sample (known /
 //      reconstructed / lost / outside) and apply the weighting function of
@@ -16,9 +16,11 @@
 //      r -= dc * phi_u;
 //   E  the model of Eq. (1) evaluated on the lost samples of the block (sums
 //      in double), written back as reconstructed samples.
-// Spectrum layout in the iteration: wave w owns rows k1 = 16w .. 16w+15, lane
-// l owns column k2 = l, so every lane keeps 16 complex entries in registers
-// and reads W[k - u] from LDS with a per-lane column offset.
+// Spectrum layout in the iteration: wavefront w owns rows k1 = ROWS*w ..
+// ROWS*w + ROWS-1 (ROWS = 64 / WAVES), lane l owns column k2 = l, so every lane
+// keeps ROWS complex entries in registers and reads W[k - u] from LDS with a
+// per-lane column offset.  WAVES = 4 is the throughput shape; WAVES = 16
+// quarters the serial work per iteration for waves too small to fill the GPU.
 #include <hip/hip_runtime.h>
 
 #include "fse_device.h"
@@ -34,10 +36,10 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
-// 16 spectrum entries of one lane.  A vector type keeps them in registers
+// The spectrum entries of one lane.  A vector type keeps them in registers
 // even when indexed by a wave-uniform run-time index (register-indexed move).
-template <typename T>
-using Vec16 = T __attribute__((ext_vector_type(16)));
+template <typename T, int R>
+using VecR = T __attribute__((ext_vector_type(R)));
 
 template <typename T>
 __device__ __forceinline__ T read_lane(T v, int lane);
@@ -55,13 +57,14 @@ __device__ __forceinline__ double read_lane<double>(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// One DPP step of a wavefront max: x = max(x, x moved by `ctrl`).  Lanes
-// outside row_mask keep their own value, so the step is idempotent there.
+// One DPP step of a wavefront max: x = max(x, x moved by CTRL).  Lanes
+// outside ROWMASK keep their own value, so the step is idempotent there.
+// Unsigned max has identity 0, so lanes without a source (or outside
+// ROWMASK) may read 0; this lets the move fold into v_max_u32 with DPP.
 template <int CTRL, int ROWMASK>
-__device__ __forceinline__ float dpp_max_step(float x) {
-  int y = __builtin_amdgcn_update_dpp(__float_as_int(x), __float_as_int(x), CTRL, ROWMASK, 0xF,
-                                      false);
-  return fmaxf(x, __int_as_float(y));
+__device__ __forceinline__ unsigned dpp_max_step(unsigned x) {
+  unsigned y = (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROWMASK, 0xF, true);
+  return x > y ? x : y;
 }
 
 template <int CTRL, int ROWMASK>
@@ -74,72 +77,64 @@ __device__ __forceinline__ double dpp_max_step(double x) {
   return fmax(x, y);
 }
 
-// Wavefront maximum (exact: max is order-free); returned uniform.
-template <typename T>
-__device__ __forceinline__ T wave_max(T x) {
+// Wavefront maximum (exact: max is order-free), returned uniform.
+template <typename V>
+__device__ __forceinline__ V wave_max(V x) {
   x = dpp_max_step<0xB1, 0xF>(x);   // quad_perm [1,0,3,2]
   x = dpp_max_step<0x4E, 0xF>(x);   // quad_perm [2,3,0,1]
   x = dpp_max_step<0x124, 0xF>(x);  // row_ror:4
   x = dpp_max_step<0x128, 0xF>(x);  // row_ror:8 -> every lane holds its row max
   x = dpp_max_step<0x142, 0xA>(x);  // row_bcast:15 -> rows 1, 3
   x = dpp_max_step<0x143, 0xC>(x);  // row_bcast:31 -> row 3 holds the wave max
-  return read_lane(x, 63);
+  if constexpr (sizeof(V) == 4) {
+    return (V)__builtin_amdgcn_readlane((int)x, 63);
+  } else {
+    return read_lane(x, 63);
+  }
 }
 
-template <typename T>
-__device__ __forceinline__ T max3(T a, T b, T c) {
-  return fmax(a, fmax(b, c));
-}
-template <>
-__device__ __forceinline__ float max3<float>(float a, float b, float c) {
-  return fmaxf(a, fmaxf(b, c));
+__device__ __forceinline__ unsigned umax3(unsigned a, unsigned b, unsigned c) {
+  return max(a, max(b, c));
 }
 
-// Result of one wavefront's argmax, exchanged through LDS.
-template <typename T>
+// (bits & ~63) | (low & 63) as one bit-field insert (the compiler otherwise
+// splits it into two operations).
+__device__ __forceinline__ unsigned pack_key(unsigned bits, unsigned low) {
+  unsigned r;
+  asm("v_bfi_b32 %0, 63, %1, %2" : "=v"(r) : "s"(low), "v"(bits));
+  return r;
+}
+
+// Argmax slot exchanged between wavefronts (32 bytes).
 struct Slot {
-  T e, re, im;
-  int k;
+  double e;     // FP64 path: exact |R|^2 of the wave's best entry
+  double re, im;
+  unsigned key; // FP32 path: packed selection key of the wave's best entry
+  int k;        // its spectrum index k1 * 64 + k2
 };
 
-constexpr int kWRows = kFft + kRowsPerWave - 1;  // rows 64.. repeat rows 0..14
-
-struct Lds {
-  int64_t region, hist;
-};
-
-template <typename T>
-__device__ __forceinline__ Lds lds_layout(int M, int N, int K) {
-  const int NP = N | 1;
-  int64_t stage = 2LL * M * NP * sizeof(T) + 2LL * M * kHalf * 2 * sizeof(T);
-  int64_t wreg = (int64_t)kWRows * kFft * 2 * sizeof(T);
-  int64_t region = stage > wreg ? stage : wreg;
-  region = (region + 15) & ~15LL;
-  int64_t hist = (int64_t)K * (2 * sizeof(T)) + (int64_t)K * sizeof(int32_t);
-  hist = (hist + 15) & ~15LL;
-  return {region, hist};
-}
-
-template <typename T>
-__global__ __launch_bounds__(kThreads) void fse_block_kernel(BlockArgs<T> a) {
+template <typename T, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void fse_block_kernel(BlockArgs<T> a) {
+  constexpr int THREADS = 64 * WAVES;
+  constexpr int ROWS = kFft / WAVES;
+  constexpr int QB = (kHalf + WAVES - 1) / WAVES;  // row-DFT columns per wavefront
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = uniform_int(tid >> 6);
   const int M = a.M, N = a.N, NP = N | 1, K = a.K;
 
-  const Lds L = lds_layout<T>(M, N, K);
+  const LdsLayout L = lds_layout(M, N, K, WAVES, (int)sizeof(T));
   T* xs = reinterpret_cast<T*>(smem);
   T* ws = xs + M * NP;
-  T* bx = ws + M * NP;
-  T* bw = bx + M * kHalf * 2;
-  T* Wl = reinterpret_cast<T*>(smem);  // kWRows x 64 complex, after phase C
-  T* hdc = reinterpret_cast<T*>(smem + L.region);
-  int* hu = reinterpret_cast<int*>(hdc + 2 * K);
-  double* tw = reinterpret_cast<double*>(smem + L.region + L.hist);  // 64 x (cos, sin)
-  T* twt = reinterpret_cast<T*>(tw + 2 * kFft);                      // same, in T
-  Slot<T>* slots = reinterpret_cast<Slot<T>*>(twt + 2 * kFft);       // 2 x 4
-  double* misc = reinterpret_cast<double*>(slots + 2 * kWaves);
+  T* bx = reinterpret_cast<T*>(smem + L.bx);
+  T* bw = reinterpret_cast<T*>(smem + L.bw);
+  T* Wl = reinterpret_cast<T*>(smem);  // (64 + ROWS - 1) x 64 complex, after phase C
+  T* hdc = reinterpret_cast<T*>(smem + L.hist_dc);
+  int* hu = reinterpret_cast<int*>(smem + L.hist_u);
+  double* tw = reinterpret_cast<double*>(smem + L.tw64);
+  T* twt = reinterpret_cast<T*>(smem + L.twt);
+  Slot* slots = reinterpret_cast<Slot*>(smem + L.slots);
 
   const int item = blockIdx.x;
   const int fr = a.items[2 * item];
@@ -160,7 +155,7 @@ __global__ __launch_bounds__(kThreads) void fse_block_kernel(BlockArgs<T> a) {
 
   // ---- A: gather, classify, weight (Eq. (2)) ----
   T wsum = T(0);
-  for (int i = tid; i < M * N; i += kThreads) {
+  for (int i = tid; i < M * N; i += THREADS) {
     const int m = i / N, n = i - m * N;
     const int y = oy + m, x = ox + n;
     T wv = T(0), xv = T(0);
@@ -176,22 +171,24 @@ __global__ __launch_bounds__(kThreads) void fse_block_kernel(BlockArgs<T> a) {
     wsum += wv;
   }
   wsum = wave_sum(wsum);
-  if (lane == 0) misc[wave] = (double)wsum;
+  if (lane == 0) slots[wave].e = (double)wsum;
   __syncthreads();
-  const T W0 = ((T)misc[0] + (T)misc[1]) + ((T)misc[2] + (T)misc[3]);
+  T W0 = T(0);
+#pragma unroll
+  for (int q = 0; q < WAVES; ++q) W0 += (T)slots[q].e;
 
   if (W0 > T(0)) {
-    // ---- B: real row DFTs, columns k2 = wave + 4q (q = 0..8), k2 <= 32 ----
+    // ---- B: real row DFTs, columns k2 = wave + WAVES q, k2 <= 32 ----
     {
-      T axr[9], axi[9], awr[9], awi[9];
+      T axr[QB], axi[QB], awr[QB], awi[QB];
 #pragma unroll
-      for (int q = 0; q < 9; ++q) axr[q] = axi[q] = awr[q] = awi[q] = T(0);
+      for (int q = 0; q < QB; ++q) axr[q] = axi[q] = awr[q] = awi[q] = T(0);
       if (lane < M) {
         for (int n = 0; n < N; ++n) {
           const T xv = xs[lane * NP + n], wv = ws[lane * NP + n];
 #pragma unroll
-          for (int q = 0; q < 9; ++q) {
-            const int t = ((wave + 4 * q) * n) & (kFft - 1);
+          for (int q = 0; q < QB; ++q) {
+            const int t = ((wave + WAVES * q) * n) & (kFft - 1);
             const T c = twt[2 * t], s = twt[2 * t + 1];
             axr[q] = fma(xv, c, axr[q]);
             axi[q] = fma(-xv, s, axi[q]);
@@ -200,8 +197,8 @@ __global__ __launch_bounds__(kThreads) void fse_block_kernel(BlockArgs<T> a) {
           }
         }
 #pragma unroll
-        for (int q = 0; q < 9; ++q) {
-          const int k2 = wave + 4 * q;
+        for (int q = 0; q < QB; ++q) {
+          const int k2 = wave + WAVES * q;
           if (k2 < kHalf) {
             T* px = bx + (lane * kHalf + k2) * 2;
             T* pw = bw + (lane * kHalf + k2) * 2;
@@ -215,21 +212,21 @@ __global__ __launch_bounds__(kThreads) void fse_block_kernel(BlockArgs<T> a) {
     }
     __syncthreads();
 
-    // ---- C: column DFT of z = x + j s w for k1 = 16 wave + j, k2 = lane ----
-    Vec16<T> rr, ri;
+    // ---- C: column DFT of z = x + j s w for k1 = ROWS wave + j, k2 = lane ----
+    VecR<T, ROWS> rr, ri;
     {
       const int c = lane <= 32 ? lane : kFft - lane;
       const T sg = lane <= 32 ? T(1) : T(-1);  // conjugate mirrored columns
       const T zs = a.zscale;
 #pragma unroll
-      for (int j = 0; j < kRowsPerWave; ++j) rr[j] = ri[j] = T(0);
+      for (int j = 0; j < ROWS; ++j) rr[j] = ri[j] = T(0);
       for (int m = 0; m < M; ++m) {
         const T xr = bx[(m * kHalf + c) * 2], xi = sg * bx[(m * kHalf + c) * 2 + 1];
         const T wr = bw[(m * kHalf + c) * 2], wi = sg * bw[(m * kHalf + c) * 2 + 1];
         const T zr = fma(-zs, wi, xr), zi = fma(zs, wr, xi);
 #pragma unroll
-        for (int j = 0; j < kRowsPerWave; ++j) {
-          const int t = ((kRowsPerWave * wave + j) * m) & (kFft - 1);
+        for (int j = 0; j < ROWS; ++j) {
+          const int t = ((ROWS * wave + j) * m) & (kFft - 1);
           const T cc = twt[2 * t], ss = twt[2 * t + 1];
           rr[j] = fma(zr, cc, fma(zi, ss, rr[j]));
           ri[j] = fma(zi, cc, fma(-zr, ss, ri[j]));
@@ -238,19 +235,19 @@ __global__ __launch_bounds__(kThreads) void fse_block_kernel(BlockArgs<T> a) {
     }
     __syncthreads();  // phase-B buffers are dead from here on
 #pragma unroll
-    for (int j = 0; j < kRowsPerWave; ++j) {
-      T* p = Wl + ((kRowsPerWave * wave + j) * kFft + lane) * 2;
+    for (int j = 0; j < ROWS; ++j) {
+      T* p = Wl + ((ROWS * wave + j) * kFft + lane) * 2;
       p[0] = rr[j];
       p[1] = ri[j];
     }
     __syncthreads();
     // unpack: X[k] = (Z[k] + conj Z[-k]) / 2, W[k] = (Z[k] - conj Z[-k]) / (2 j s)
-    T wvr[kRowsPerWave], wvi[kRowsPerWave];
+    T wvr[ROWS], wvi[ROWS];
     {
       const T h = T(0.5), hs = T(0.5) / a.zscale;
 #pragma unroll
-      for (int j = 0; j < kRowsPerWave; ++j) {
-        const int k1 = kRowsPerWave * wave + j;
+      for (int j = 0; j < ROWS; ++j) {
+        const int k1 = ROWS * wave + j;
         const T* p = Wl + ((((kFft - k1) & (kFft - 1)) * kFft) + ((kFft - lane) & (kFft - 1))) * 2;
         const T pr = p[0], pi = p[1];
         const T ar = rr[j], ai = ri[j];
@@ -262,12 +259,12 @@ __global__ __launch_bounds__(kThreads) void fse_block_kernel(BlockArgs<T> a) {
     }
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < kRowsPerWave; ++j) {
-      const int row = kRowsPerWave * wave + j;
+    for (int j = 0; j < ROWS; ++j) {
+      const int row = ROWS * wave + j;
       T* p = Wl + (row * kFft + lane) * 2;
       p[0] = wvr[j];
       p[1] = wvi[j];
-      if (row < kWRows - kFft) {  // wrap-around copy: a wave's 16 rows never wrap
+      if (row < ROWS - 1) {  // wrap-around copy: a wave's ROWS rows never wrap
         T* q = Wl + ((row + kFft) * kFft + lane) * 2;
         q[0] = wvr[j];
         q[1] = wvi[j];
@@ -277,18 +274,23 @@ __global__ __launch_bounds__(kThreads) void fse_block_kernel(BlockArgs<T> a) {
 
     // ---- D: K greedy iterations ----
     // Each iteration first applies the previous selection's update (a zero
-    // update in the first iteration), then selects u = argmax |R|^2 with ties
-    // to the smallest row-major index, and forms the coefficient increment.
+    // update in the first iteration), then selects u = argmax |R|^2 and forms
+    // the coefficient increment.
+    //  FP64: exact |R|^2, ties to the smallest row-major index.
+    //  FP32: |R|^2 compared with its 6 lowest mantissa bits replaced by
+    //        63 - k1 (a relative resolution of 2^-17, below the rounding
+    //        drift of a float spectrum), so one unsigned max gives value and
+    //        row; ties go to the smallest k1, then the smallest k2.
     const T gs = a.gamma / W0;
     int u = 0;
     T dcr = T(0), dci = T(0);
     for (int it = 0; it < K; ++it) {
       const int col = (lane - (u & (kFft - 1))) & (kFft - 1);
-      const int b = uniform_int((kRowsPerWave * wave - (u >> 6)) & (kFft - 1));
+      const int b = uniform_int((ROWS * wave - (u >> 6)) & (kFft - 1));
       const T* wp = Wl + (b * kFft + col) * 2;
-      Vec16<T> e;
+      VecR<T, ROWS> e;
 #pragma unroll
-      for (int j = 0; j < kRowsPerWave; ++j) {
+      for (int j = 0; j < ROWS; ++j) {
         const T wr = wp[j * kFft * 2], wi = wp[j * kFft * 2 + 1];
         T r = rr[j], q = ri[j];
         r = fma(-dcr, wr, r);
@@ -299,52 +301,79 @@ __global__ __launch_bounds__(kThreads) void fse_block_kernel(BlockArgs<T> a) {
         ri[j] = q;
         e[j] = fma(r, r, q * q);
       }
-      T lm = max3(e[0], e[1], e[2]);
-      lm = max3(lm, e[3], e[4]);
-      lm = max3(lm, e[5], e[6]);
-      lm = max3(lm, e[7], e[8]);
-      lm = max3(lm, e[9], e[10]);
-      lm = max3(lm, e[11], e[12]);
-      lm = max3(lm, e[13], e[14]);
-      lm = fmax(lm, e[15]);
-      const T wm = wave_max(lm);
-      // first (row, lane) holding the wave maximum
-      unsigned long long hit = 0;
-      int jw = 0;
+      Slot* sl = slots + (it & 1) * WAVES;
+      if constexpr (sizeof(T) == 4) {
+        unsigned key[ROWS];
 #pragma unroll
-      for (int j = kRowsPerWave - 1; j >= 0; --j) {
-        const unsigned long long mj = __ballot(e[j] == wm);
-        if (mj) {
-          hit = mj;
-          jw = j;
+        for (int j = 0; j < ROWS; ++j)
+          key[j] = pack_key(__float_as_uint(e[j]), (unsigned)(63 - (ROWS * wave + j)));
+        unsigned lk = key[0];
+#pragma unroll
+        for (int j = 1; j + 1 < ROWS; j += 2) lk = umax3(lk, key[j], key[j + 1]);
+        if constexpr (ROWS % 2 == 0) lk = max(lk, key[ROWS - 1]);
+        const unsigned wk = wave_max(lk);
+        const unsigned long long hit = __ballot(lk == wk);
+        const int lw = uniform_int(__builtin_ctzll(hit));
+        const int jw = uniform_int(63 - (int)(wk & 63u) - ROWS * wave);
+        const T sr = read_lane((T)rr[jw], lw);
+        const T si = read_lane((T)ri[jw], lw);
+        if (lane == 0) {
+          Slot v;
+          v.key = wk;
+          v.k = ((ROWS * wave + jw) << 6) | lw;
+          v.re = sr;
+          v.im = si;
+          sl[wave] = v;
         }
-      }
-      jw = uniform_int(jw);
-      const int lw = uniform_int(__builtin_ctzll(hit));
-      // the register-indexed moves must run on every lane before the
-      // cross-lane read, so they stay outside the lane-0 branch
-      const T sr = read_lane((T)rr[jw], lw);
-      const T si = read_lane((T)ri[jw], lw);
-      Slot<T>* sl = slots + (it & 1) * kWaves;
-      if (lane == 0) {
-        Slot<T> v;
-        v.e = wm;
-        v.re = sr;
-        v.im = si;
-        v.k = ((kRowsPerWave * wave + jw) << 6) | lw;
-        sl[wave] = v;
-      }
-      __syncthreads();
-      // waves cover increasing k, so a strict > keeps the smallest k on ties
-      Slot<T> best = sl[0];
+        __syncthreads();
+        // the winning wavefront: largest key (its row is in the key)
+        unsigned gk = lane < WAVES ? sl[lane].key : 0u;
+        gk = wave_max(gk);
+        const int wwin = uniform_int((63 - (int)(gk & 63u)) / ROWS);
+        const Slot best = sl[wwin];
+        u = uniform_int(best.k);
+        dcr = gs * (T)best.re;
+        dci = gs * (T)best.im;
+      } else {
+        T lm = e[0];
 #pragma unroll
-      for (int q = 1; q < kWaves; ++q) {
-        const Slot<T> c = sl[q];
-        if (c.e > best.e) best = c;
+        for (int j = 1; j < ROWS; ++j) lm = fmax(lm, e[j]);
+        const T wm = wave_max(lm);
+        // first (row, lane) holding the wave maximum
+        unsigned long long hit = 0;
+        int jw = 0;
+#pragma unroll
+        for (int j = ROWS - 1; j >= 0; --j) {
+          const unsigned long long mj = __ballot(e[j] == wm);
+          if (mj) {
+            hit = mj;
+            jw = j;
+          }
+        }
+        jw = uniform_int(jw);
+        const int lw = uniform_int(__builtin_ctzll(hit));
+        const T sr = read_lane((T)rr[jw], lw);
+        const T si = read_lane((T)ri[jw], lw);
+        if (lane == 0) {
+          Slot v;
+          v.e = wm;
+          v.re = sr;
+          v.im = si;
+          v.k = ((ROWS * wave + jw) << 6) | lw;
+          sl[wave] = v;
+        }
+        __syncthreads();
+        // wavefronts cover increasing k, so a strict > keeps the smallest k
+        Slot best = sl[0];
+#pragma unroll
+        for (int q = 1; q < WAVES; ++q) {
+          const Slot c = sl[q];
+          if (c.e > best.e) best = c;
+        }
+        u = uniform_int(best.k);
+        dcr = gs * (T)best.re;
+        dci = gs * (T)best.im;
       }
-      u = uniform_int(best.k);
-      dcr = gs * best.re;
-      dci = gs * best.im;
       if (tid == 0) {
         hu[it] = u;
         hdc[2 * it] = dcr;
@@ -357,7 +386,7 @@ __global__ __launch_bounds__(kThreads) void fse_block_kernel(BlockArgs<T> a) {
   // ---- E: model samples on B_i (Eq. (1)), sums in double ----
   const bool empty = !(W0 > T(0));
   const int nb = a.Bh * a.Bw;
-  for (int s = tid; s < nb; s += kThreads) {
+  for (int s = tid; s < nb; s += THREADS) {
     const int dy = s / a.Bw, dx = s - dy * a.Bw;
     const int y = by0 + dy, x = bx0 + dx;
     if (y < 0 || y >= H || x < 0 || x >= W) continue;
@@ -384,7 +413,7 @@ __global__ __launch_bounds__(kThreads) void fse_block_kernel(BlockArgs<T> a) {
     }
   }
   if (a.trace_u) {
-    for (int i = tid; i < K; i += kThreads) {
+    for (int i = tid; i < K; i += THREADS) {
       a.trace_u[(int64_t)item * K + i] = empty ? -1 : hu[i];
       a.trace_dc[((int64_t)item * K + i) * 2] = empty ? T(0) : hdc[2 * i];
       a.trace_dc[((int64_t)item * K + i) * 2 + 1] = empty ? T(0) : hdc[2 * i + 1];
@@ -427,7 +456,7 @@ __global__ void fse_init_kernel(const IoDesc* io, T* work, uint8_t* state, uint8
     const bool l = d.lost[(int64_t)y * d.lstride + x] != 0;
     work[d.off + i] = l ? T(0) : (T)d.image[(int64_t)y * d.stride + x];
     state[d.off + i] = l ? kPending : kKnown;
-    if (l) flags[d.flag_off + (int64_t)((y + goy) / Bh) * d.wb + (x + gox) / Bw] = 1;
+    if (l && flags) flags[d.flag_off + (int64_t)((y + goy) / Bh) * d.wb + (x + gox) / Bw] = 1;
   }
 }
 
@@ -457,18 +486,28 @@ __global__ void fse_finalize_kernel(const IoDesc* io, const uint8_t* state, cons
 
 // ---------------------------------------------------------------- launchers
 
-template <typename T>
-hipError_t launch_block(const BlockArgs<T>& a, int n_items, size_t lds, hipStream_t s) {
-  if (n_items <= 0) return hipSuccess;
+template <typename T, int WAVES>
+static hipError_t launch_block_w(const BlockArgs<T>& a, int n_items, size_t lds, hipStream_t s) {
   static size_t attr_bytes = 0;  // largest dynamic LDS size enabled so far
   if (lds > attr_bytes) {
-    hipError_t e = hipFuncSetAttribute((const void*)fse_block_kernel<T>,
+    hipError_t e = hipFuncSetAttribute((const void*)fse_block_kernel<T, WAVES>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     attr_bytes = lds;
   }
-  hipLaunchKernelGGL(fse_block_kernel<T>, dim3(n_items), dim3(kThreads), lds, s, a);
+  hipLaunchKernelGGL((fse_block_kernel<T, WAVES>), dim3(n_items), dim3(64 * WAVES), lds, s, a);
   return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_block(const BlockArgs<T>& a, int n_items, int waves, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  const size_t lds = (size_t)lds_bytes<T>(a.M, a.N, a.K, waves);
+  switch (waves) {
+    case 4: return launch_block_w<T, 4>(a, n_items, lds, s);
+    case 16: return launch_block_w<T, 16>(a, n_items, lds, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <typename T>
@@ -504,8 +543,8 @@ hipError_t launch_finalize(const IoDesc* io, int nframes, int64_t max_pixels,
   return hipGetLastError();
 }
 
-template hipError_t launch_block<float>(const BlockArgs<float>&, int, size_t, hipStream_t);
-template hipError_t launch_block<double>(const BlockArgs<double>&, int, size_t, hipStream_t);
+template hipError_t launch_block<float>(const BlockArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_block<double>(const BlockArgs<double>&, int, int, hipStream_t);
 template hipError_t launch_scatter<float>(float*, uint8_t*, const FrameDesc*, const int32_t*, int,
                                           const float*, int, int, int, int, hipStream_t);
 template hipError_t launch_scatter<double>(double*, uint8_t*, const FrameDesc*, const int32_t*,

@@ -24,7 +24,7 @@
 namespace fse {
 
 template <typename T>
-hipError_t launch_block(const BlockArgs<T>& a, int n_items, size_t lds, hipStream_t s);
+hipError_t launch_block(const BlockArgs<T>& a, int n_items, int waves, hipStream_t s);
 template <typename T>
 hipError_t launch_scatter(T* work, uint8_t* state, const FrameDesc* frames, const int32_t* items,
                           int n_items, const T* staging, int Bh, int Bw, int gox, int goy,
@@ -276,14 +276,29 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
       st->latency_ms = 0.0;
     }
   }
+  // frames start at staggered steps; step s holds wave s - off[f] of frame f
+  std::vector<int> off(n, 0);
+  if (n > 1 && pl->stagger) {
+    std::vector<std::vector<int>> sizes(n);
+    for (int f = 0; f < n; ++f) {
+      int nw = 0;
+      for (int32_t b : seq[f]) nw = std::max(nw, wave_of[f][b] + 1);
+      sizes[f].assign(nw, 0);
+      for (int32_t b : seq[f]) ++sizes[f][wave_of[f][b]];
+    }
+    const bool fp64 = p.precision == FSE_FP64;
+    off = stagger_frames(sizes, fp64 ? pl->model_latency_us[0] : pl->model_latency_us[1],
+                         fp64 ? pl->model_rate[0] : pl->model_rate[1]);
+  }
   std::vector<int32_t> items;
   std::vector<int64_t> wave_start(max_waves + 1, 0);
   std::vector<size_t> pos(n, 0);
   std::vector<std::pair<int, int32_t>> item_src;  // (frame, block) per item
-  for (int t = 0; t < max_waves; ++t) {
-    wave_start[t] = (int64_t)items.size() / 2;
+  for (int step = 0; step < max_waves; ++step) {
+    wave_start[step] = (int64_t)items.size() / 2;
     for (int f = 0; f < n; ++f) {
-      while (pos[f] < seq[f].size() && wave_of[f][seq[f][pos[f]]] == t) {
+      const int t = step - off[f];
+      while (t >= 0 && pos[f] < seq[f].size() && wave_of[f][seq[f][pos[f]]] == t) {
         const int32_t b = seq[f][pos[f]++];
         items.push_back(f);
         items.push_back(((b / wb[f]) << 16) | (b % wb[f]));
@@ -331,7 +346,6 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
   a.gamma = (T)p.gamma;
   a.zscale = (T)128.0;
   a.empty_fill = p.empty_fill;
-  const size_t lds = (size_t)lds_bytes<T>(pl->M, pl->N, K);
 
   while ((int)pl->events.size() < 2 * max_waves) {
     hipEvent_t e;
@@ -345,7 +359,8 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
     a.trace_u = want_trace ? (int32_t*)pl->trace_u.ptr + i0 * K : nullptr;
     a.trace_dc = want_trace ? (T*)pl->trace_dc.ptr + i0 * K * 2 : nullptr;
     if ((rc = chk(hipEventRecord(pl->events[2 * t], s)))) return rc;
-    if ((rc = chk(launch_block<T>(a, (int)cnt, lds, s)))) return rc;
+    const int waves = cnt <= pl->wide_threshold ? 16 : 4;
+    if ((rc = chk(launch_block<T>(a, (int)cnt, waves, s)))) return rc;
     if ((rc = chk(hipEventRecord(pl->events[2 * t + 1], s)))) return rc;
     if (staged && (rc = chk(launch_scatter<T>(work, state, a.frames, a.items, (int)cnt,
                                               (const T*)pl->staging.ptr, Bh, Bw, gox, goy, s))))
@@ -434,8 +449,11 @@ int32_t fse_plan(const fse_params* p, void* hip_stream, fse_plan_t* out) {
   if (hipGetDevice(&dev) != hipSuccess) return FSE_ERR_DEVICE;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return FSE_ERR_DEVICE;
-  const int64_t need = p->precision == FSE_FP64 ? lds_bytes<double>(M, N, K) : lds_bytes<float>(M, N, K);
-  if (need > (int64_t)prop.sharedMemPerBlock) return FSE_ERR_UNSUPPORTED;
+  for (int waves : {4, 16}) {
+    const int64_t need = p->precision == FSE_FP64 ? lds_bytes<double>(M, N, K, waves)
+                                                  : lds_bytes<float>(M, N, K, waves);
+    if (need > (int64_t)prop.sharedMemPerBlock) return FSE_ERR_UNSUPPORTED;
+  }
   fse_plan_s* pl = new fse_plan_s();
   pl->p = *p;
   pl->M = M;

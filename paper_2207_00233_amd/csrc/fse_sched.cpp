@@ -11,6 +11,7 @@
 // smallest non-negative N and that touches no block already taken for this
 // wave; after the wave every taken block is finished and its pending
 // neighbours lose one not-extrapolated neighbour.
+#include <algorithm>
 #include <cstdint>
 #include <vector>
 
@@ -87,6 +88,49 @@ int schedule_blocks(int hb, int wb, const uint8_t* lost, int order, int32_t* wav
     ++wave;
   }
   return wave;
+}
+
+// Staggered start of the frames of a batch.  Launch step s runs wave s - off[f]
+// of every frame f (when that wave exists), so each frame keeps its own wave
+// order and gets exactly its stand-alone result; only which waves share a
+// launch changes.  A launch costs about max(latency, blocks / rate), so the
+// offsets move the large early waves of short frames onto the steps where the
+// long frames only have small waves.  Greedy: frames by decreasing wave count,
+// each at the offset (within the longest frame's span) that adds least cost.
+std::vector<int> stagger_frames(const std::vector<std::vector<int>>& sizes, double latency_us,
+                                double blocks_per_us) {
+  const int n = (int)sizes.size();
+  int T = 0;
+  for (const auto& v : sizes) T = std::max<int>(T, (int)v.size());
+  std::vector<int> off(n, 0), order(n);
+  for (int f = 0; f < n; ++f) order[f] = f;
+  auto total = [&](int f) {
+    long t = 0;
+    for (int x : sizes[f]) t += x;
+    return t;
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    if (sizes[a].size() != sizes[b].size()) return sizes[a].size() > sizes[b].size();
+    return total(a) > total(b);
+  });
+  auto cost = [&](double x) { return x <= 0 ? 0.0 : std::max(latency_us, x / blocks_per_us); };
+  std::vector<double> load(T, 0.0);
+  for (int f : order) {
+    const int nw = (int)sizes[f].size();
+    int best_o = 0;
+    double best_c = 0;
+    for (int o = 0; o + nw <= T; ++o) {
+      double c = 0;
+      for (int t = 0; t < nw; ++t) c += cost(load[o + t] + sizes[f][t]) - cost(load[o + t]);
+      if (o == 0 || c < best_c - 1e-9) {
+        best_c = c;
+        best_o = o;
+      }
+    }
+    off[f] = best_o;
+    for (int t = 0; t < nw; ++t) load[best_o + t] += sizes[f][t];
+  }
+  return off;
 }
 
 }  // namespace fse

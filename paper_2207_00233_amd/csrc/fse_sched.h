@@ -11,4 +11,9 @@ namespace fse {
 int schedule_blocks(int hb, int wb, const uint8_t* lost, int order, int32_t* wave_of,
                     std::vector<int32_t>* seq);
 
+// Start offsets (in launch steps) for the frames of a batch; sizes[f][t] is the
+// number of blocks of wave t of frame f.  See fse_sched.cpp.
+std::vector<int> stagger_frames(const std::vector<std::vector<int>>& sizes, double latency_us,
+                                double blocks_per_us);
+
 }  // namespace fse

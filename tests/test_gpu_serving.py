@@ -1,0 +1,99 @@
+"""Serving (fse_submit / fse_poll) on the GPU: every frame's result is the
+same alone (fse_conceal_image) and in the continuously batched mix,
+admission respects the device memory budget, and the error paths of the
+ticket interface."""
+import numpy as np
+import pytest
+
+import paper_2207_00233_amd as fse
+from paper_2207_00233_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _frames(seed, sizes):
+    rng = np.random.default_rng(seed)
+    out = []
+    for (H, W) in sizes:
+        img = synth.polygon_image(rng, H, W, radius=(8, 40))
+        out.append((img, synth.slice_loss(rng, H, W, 16, (0.1, 0.3))))
+    return out
+
+
+def _alone(p, frames):
+    with fse.Plan(p) as plan:
+        return [plan.fse_conceal_image([im], [ls], want_float=True)[0] for im, ls in frames]
+
+
+@pytest.mark.parametrize("precision", [fse.FSE_FP32, fse.FSE_FP64])
+def test_served_results_equal_alone(precision):
+    frames = _frames(1, [(96, 128), (45, 70), (128, 96), (64, 64), (80, 112), (33, 47)])
+    p = fse.Params(border_d=14, iterations=60, precision=precision)
+    ref = _alone(p, frames)
+    print(f"[serve] precision={precision} submitting {len(frames)} frames", flush=True)
+    with fse.Plan(p) as plan:
+        tickets = [plan.fse_submit(im, ls, want_float=True) for im, ls in frames]
+        res = [plan.fse_poll(t, timeout_us=-1) for t in tickets]
+    for r, a in zip(res, ref):
+        np.testing.assert_array_equal(r.out, a.out)
+        np.testing.assert_array_equal(r.out_f, a.out_f)
+        assert r.waves == a.waves and r.lost_blocks == a.lost_blocks
+        assert r.latency_ms > 0
+
+
+def test_admission_under_a_small_budget():
+    # the budget holds about two of these frames at a time
+    frames = _frames(2, [(96, 128)] * 7)
+    per_frame = 96 * 128 * (4 + 4)
+    p = fse.Params(border_d=14, iterations=30, precision=fse.FSE_FP32,
+                   device_mem_budget=int(2.5 * per_frame), max_inflight_frames=16)
+    ref = _alone(fse.Params(border_d=14, iterations=30, precision=fse.FSE_FP32), frames)
+    with fse.Plan(p) as plan:
+        tickets = [plan.fse_submit(im, ls) for im, ls in frames]
+        res = [plan.fse_poll(t, timeout_us=-1) for t in tickets]
+        # a frame larger than the whole budget can never be admitted
+        big = np.zeros((256, 256), np.uint8)
+        with pytest.raises(fse.FseError) as ei:
+            plan.fse_submit(big, np.ones_like(big))
+        assert ei.value.code == fse.FSE_ERR_NOMEM
+    for r, a in zip(res, ref):
+        np.testing.assert_array_equal(r.out, a.out)
+
+
+def test_queue_full_and_ticket_errors():
+    frames = _frames(3, [(64, 64)] * 3)
+    p = fse.Params(border_d=14, iterations=200, precision=fse.FSE_FP32, max_inflight_frames=2)
+    with fse.Plan(p) as plan:
+        t0 = plan.fse_submit(*frames[0])
+        t1 = plan.fse_submit(*frames[1])
+        with pytest.raises(fse.FseError) as ei:
+            plan.fse_submit(*frames[2])
+        assert ei.value.code == fse.FSE_ERR_AGAIN
+        plan.fse_poll(t0, timeout_us=-1)
+        plan.fse_poll(t1, timeout_us=-1)
+        t2 = plan.fse_submit(*frames[2])   # room again
+        plan.fse_poll(t2, timeout_us=-1)
+        lib = fse.load()
+        assert lib.fse_poll(plan.handle, t2, 0) == fse.FSE_ERR_TICKET   # consumed
+        assert lib.fse_poll(plan.handle, 987654, 0) == fse.FSE_ERR_TICKET
+
+
+def test_poll_without_waiting_reports_pending_then_done():
+    frames = _frames(4, [(128, 128)])
+    p = fse.Params(border_d=14, iterations=200, precision=fse.FSE_FP32)
+    with fse.Plan(p) as plan:
+        t = plan.fse_submit(*frames[0])
+        first = plan.fse_poll(t, timeout_us=0)
+        assert first == fse.FSE_PENDING or isinstance(first, fse.Result)
+        if first == fse.FSE_PENDING:
+            r = plan.fse_poll(t, timeout_us=-1)
+            assert isinstance(r, fse.Result)
+
+
+def test_destroy_with_frames_in_flight():
+    frames = _frames(5, [(96, 96)] * 4)
+    p = fse.Params(border_d=14, iterations=200, precision=fse.FSE_FP32)
+    plan = fse.Plan(p)
+    for im, ls in frames:
+        plan.fse_submit(im, ls)
+    plan.close()   # waits for in-flight work, frees everything
