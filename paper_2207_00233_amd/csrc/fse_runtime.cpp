@@ -8,12 +8,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <thread>
 #include <vector>
 
 #include "fse.h"
@@ -257,9 +259,28 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
   // processing order per frame, merged by wave index
   std::vector<std::vector<int32_t>> wave_of(n), seq(n);
   int max_waves = 0;
+  // frames are scheduled independently, on up to 16 host threads
+  std::vector<int> nwaves(n, 0);
+  {
+    auto run = [&](int f) {
+      wave_of[f].resize((size_t)hb[f] * wb[f]);
+      nwaves[f] = schedule_blocks(hb[f], wb[f], flags[f], p.order, wave_of[f].data(), &seq[f]);
+    };
+    const int nt = std::min<int>(n, std::min(16u, std::max(1u, std::thread::hardware_concurrency())));
+    if (nt <= 1) {
+      for (int f = 0; f < n; ++f) run(f);
+    } else {
+      std::atomic<int> next{0};
+      std::vector<std::thread> pool;
+      for (int t = 0; t < nt; ++t)
+        pool.emplace_back([&] {
+          for (int f = next++; f < n; f = next++) run(f);
+        });
+      for (auto& th : pool) th.join();
+    }
+  }
   for (int f = 0; f < n; ++f) {
-    wave_of[f].resize((size_t)hb[f] * wb[f]);
-    int nw = schedule_blocks(hb[f], wb[f], flags[f], p.order, wave_of[f].data(), &seq[f]);
+    const int nw = nwaves[f];
     max_waves = std::max(max_waves, nw);
     if (frames[f].stats) {
       fse_stats* st = frames[f].stats;
