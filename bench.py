@@ -147,6 +147,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--precision", choices=("fp32", "fp32_rerank"), default="fp32_rerank",
+                    help="arithmetic of the headline batched run")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 512 MiB device copy 3 times (HBM counter scale)")
@@ -182,32 +185,50 @@ def main():
               "width": i.shape[1], "height": i.shape[0]} for i, l, o in zip(imgs, losts, outs)]
     stream = torch.cuda.current_stream().cuda_stream
 
-    p = fse.Params(border_d=BORDER, iterations=K_ITER, precision=fse.FSE_FP32,
-                   flags=fse.FSE_FLAG_DEVICE_PTRS)
-    plan = fse.Plan(p, hip_stream=stream)
-    log("[bench] FP32 batched: warmup")
-    for _ in range(args.warmup):
-        plan.conceal_device(descs)
-    torch.cuda.synchronize()
-    kms, launches, blocks = 0.0, 0, 0
-    log(f"[bench] FP32 batched: {args.steps} timed steps")
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plan.conceal_device(descs)
-        cs = plan.last_call_stats()
-        kms += cs["kernel_ms"]
-        launches += cs["launches"]
-        blocks += cs["blocks"]
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    plan.close()
-    lost_blocks = blocks // args.steps
-    value = blocks / dt
-    avg_launch_ms = kms / max(1, launches)
-    blocks_per_launch = blocks / max(1, launches)
+    def batched(precision, steps, warmup):
+        p = fse.Params(border_d=BORDER, iterations=K_ITER, precision=precision,
+                       flags=fse.FSE_FLAG_DEVICE_PTRS)
+        plan = fse.Plan(p, hip_stream=stream)
+        for _ in range(warmup):
+            plan.conceal_device(descs)
+        torch.cuda.synchronize()
+        kms, launches, blocks = 0.0, 0, 0
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.conceal_device(descs)
+            cs = plan.last_call_stats()
+            kms += cs["kernel_ms"]
+            launches += cs["launches"]
+            blocks += cs["blocks"]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        plan.close()
+        return {"value": blocks / dt, "ms_per_step": dt / steps * 1e3,
+                "kernel_ms_per_step": kms / steps, "launches_per_step": launches // steps,
+                "blocks_per_step": blocks // steps, "avg_launch_ms": kms / max(1, launches),
+                "blocks_per_launch": blocks / max(1, launches)}
+
+    names = {fse.FSE_FP32: "fp32", fse.FSE_FP32_RERANK: "fp32_rerank", fse.FSE_FP64: "fp64"}
+    head_prec = {"fp32": fse.FSE_FP32, "fp32_rerank": fse.FSE_FP32_RERANK}[args.precision]
+    log(f"[bench] batched {args.precision}: {args.steps} timed steps")
+    head = batched(head_prec, args.steps, args.warmup)
+    log(f"[bench] batched {args.precision}: {head['value']:.0f} blocks/s, "
+        f"{head['ms_per_step']:.1f} ms/step, kernel {head['kernel_ms_per_step']:.1f} ms/step")
+    sweep = {names[head_prec]: head}
+    if not args.no_sweep:
+        for prec in (fse.FSE_FP32, fse.FSE_FP32_RERANK, fse.FSE_FP64):
+            if prec == head_prec:
+                continue
+            r = batched(prec, 2, 1)
+            sweep[names[prec]] = r
+            log(f"[bench] batched {names[prec]}: {r['value']:.0f} blocks/s")
+    value = head["value"]
+    dt = head["ms_per_step"] * args.steps / 1e3
+    lost_blocks = head["blocks_per_step"]
+    launches = head["launches_per_step"] * args.steps
+    avg_launch_ms = head["avg_launch_ms"]
+    blocks_per_launch = head["blocks_per_launch"]
     achieved = FLOPS_PER_BLOCK * blocks_per_launch / (avg_launch_ms * 1e-3) / 1e12
-    log(f"[bench] FP32 batched: {value:.0f} blocks/s, {dt / args.steps * 1e3:.1f} ms/step, "
-        f"kernel {kms / args.steps:.1f} ms/step over {launches // args.steps} launches")
 
     fp64 = None
     if not args.no_fp64:
@@ -256,19 +277,24 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
+        "precision": args.precision,
         "data": "synthetic",
         "config": {"workload": "64 mixed-resolution frames (16 each 352x288, 704x576, "
                                "1280x720, 1920x1080), 5-30% slice losses, 16x16 blocks, "
-                               "d=14, 64x64 DFT basis, K=200, FP32 batched",
+                               "d=14, 64x64 DFT basis, K=200, FP32 iterations batched"
+                               + (" with FP64 transforms and near-tie re-ranking"
+                                  if args.precision == "fp32_rerank" else ""),
                    "lost_blocks_per_step": lost_blocks, "frames": len(frames),
                    "launches_per_step": launches // args.steps},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-                     "kernel": "fse_block_kernel<float>",
+                     "kernel": "fse_block_kernel<float>" + (" + fse_dft64_kernel"
+                                                            if args.precision == "fp32_rerank" else ""),
                      "avg_launch_ms": avg_launch_ms, "blocks_per_launch": blocks_per_launch,
                      "flops_per_block": FLOPS_PER_BLOCK,
                      "frac_of_published_fp32_peak": achieved / PEAK_FP32_PUBLISHED},
         "fp64_plain": fp64,
+        "precision_sweep": sweep,
         "p99_frame_latency_ms": serving["p99_frame_latency_ms"] if serving else None,
         "serving": serving,
         "cpu_baseline": cpu,

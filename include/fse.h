@@ -59,8 +59,12 @@ enum { FSE_ORDER_OPTIMIZED = 0, FSE_ORDER_LINESCAN = 1 };
 
 /* Arithmetic of the per-block iteration. */
 enum {
-  FSE_FP64 = 0, /* spectra, weights, coefficients in double */
-  FSE_FP32 = 1  /* spectra and iteration in float; synthesis sums in double */
+  FSE_FP64 = 0,        /* spectra, weights, coefficients in double */
+  FSE_FP32 = 1,        /* spectra and iteration in float; synthesis sums in double */
+  FSE_FP32_RERANK = 2  /* transforms in double, iteration in float; whenever another
+                          spectrum entry comes within rerank_gap (relative) of the
+                          selected maximum of |R|^2, the candidates are re-scored
+                          exactly in double (R0 - sum dc_i W[k - u_i]) */
 };
 
 /* fse_params.flags */
@@ -75,7 +79,7 @@ typedef struct {
   double gamma;             /* orthogonality deficiency compensation, (0, 1] */
   int32_t iterations;       /* K, 1..FSE_MAX_ITERATIONS */
   int32_t order;            /* FSE_ORDER_* */
-  int32_t precision;        /* FSE_FP64 or FSE_FP32 */
+  int32_t precision;        /* FSE_FP64, FSE_FP32 or FSE_FP32_RERANK */
   int32_t grid_off_x;       /* block grid shift, 0 <= off < block size: */
   int32_t grid_off_y;       /*   block column j covers x in
                                [j*block_w - grid_off_x, +block_w) */
@@ -83,6 +87,7 @@ typedef struct {
   int64_t device_mem_budget;   /* bytes for serving frames; 0 = 4 GiB */
   int32_t max_inflight_frames; /* serving slots; 0 = 64 */
   int32_t flags;               /* FSE_FLAG_* */
+  double rerank_gap;           /* FSE_FP32_RERANK: relative gap, [0, 0.5); 0 = 1e-4 */
 } fse_params;
 
 #define FSE_MAX_ITERATIONS 1024

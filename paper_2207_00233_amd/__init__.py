@@ -32,6 +32,7 @@ FSE_ORDER_OPTIMIZED = 0
 FSE_ORDER_LINESCAN = 1
 FSE_FP64 = 0
 FSE_FP32 = 1
+FSE_FP32_RERANK = 2
 FSE_FLAG_DEVICE_PTRS = 1
 
 EXPORTED = ("fse_plan", "fse_plan_destroy", "fse_conceal_image", "fse_submit",
@@ -63,6 +64,7 @@ class _Params(ctypes.Structure):
         ("device_mem_budget", ctypes.c_int64),
         ("max_inflight_frames", ctypes.c_int32),
         ("flags", ctypes.c_int32),
+        ("rerank_gap", ctypes.c_double),
     ]
 
 
@@ -115,6 +117,7 @@ class Params:
     device_mem_budget: int = 0
     max_inflight_frames: int = 0
     flags: int = 0
+    rerank_gap: float = 0.0
 
     def c(self) -> _Params:
         return _Params(**dataclasses.asdict(self))
@@ -204,7 +207,8 @@ class _HostFrame:
             raise ValueError("image and lost must be 2-D arrays of the same shape")
         H, W = self.image.shape
         self.out = np.zeros((H, W), np.uint8)
-        self.of32 = np.zeros((H, W), np.float32) if want_float and precision == FSE_FP32 else None
+        self.of32 = (np.zeros((H, W), np.float32)
+                     if want_float and precision in (FSE_FP32, FSE_FP32_RERANK) else None)
         self.of64 = np.zeros((H, W), np.float64) if want_float and precision == FSE_FP64 else None
         self.stats = _Stats()
         self.trace = None

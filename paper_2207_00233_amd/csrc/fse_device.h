@@ -45,7 +45,17 @@ struct BlockArgs {
   int32_t M, N, Bh, Bw, d, gox, goy, K;
   T delta, gamma, zscale;  // zscale balances x and w in the packed DFT
   double empty_fill;
+  double delta64, gamma64; // the same parameters in double (FP64 transforms, re-rank)
+  double* spec64;          // FP64 spectra per work item (re-rank mode), see below
+  double rerank_gap;       // relative |R|^2 gap that triggers an FP64 re-rank
 };
+
+// FP64 spectra of one work item written by the FP64 transform pass of the
+// re-rank mode: R0 (64 x 64 complex), W (64 x 64 complex), then W0.
+constexpr int64_t kSpecR0 = 0;                      // in doubles
+constexpr int64_t kSpecW = 2 * kFft * kFft;
+constexpr int64_t kSpecW0 = 4 * kFft * kFft;
+constexpr int64_t kSpecStride = 4 * kFft * kFft + 32;  // doubles per item (256-byte aligned)
 
 // Byte offsets of the dynamic LDS regions of the fused block kernel with
 // `waves` wavefronts per workgroup (rows = 64 / waves spectrum rows each).
@@ -56,20 +66,24 @@ struct LdsLayout {
   int64_t tw64;      // 64 x (cos, sin) in double
   int64_t twt;       // the same in T
   int64_t slots;     // 2 x waves argmax slots of 32 bytes
+  int64_t cand;      // re-rank: 2 x waves exact-candidate slots of 32 bytes
   int64_t misc;      // 32 bytes
   int64_t total;
 };
 
 __host__ __device__ inline int64_t align16(int64_t v) { return (v + 15) & ~15LL; }
 
-__host__ __device__ inline LdsLayout lds_layout(int M, int N, int K, int waves, int tsize) {
+// `stage` = false for the re-rank iteration kernel, which receives its
+// spectra from the FP64 transform pass and needs no transform staging.
+__host__ __device__ inline LdsLayout lds_layout(int M, int N, int K, int waves, int tsize,
+                                                bool stage_needed = true) {
   LdsLayout L;
   const int NP = N | 1;  // odd row pitch of the staged area
   const int rows = kFft / waves;
   const int64_t stage_xw = 2LL * M * NP * tsize;
   L.bx = stage_xw;
   L.bw = L.bx + (int64_t)M * kHalf * 2 * tsize;
-  const int64_t stage = L.bw + (int64_t)M * kHalf * 2 * tsize;
+  const int64_t stage = stage_needed ? L.bw + (int64_t)M * kHalf * 2 * tsize : 0;
   // the W spectrum with rows - 1 wrap-around rows (rows 64.. repeat 0..)
   const int64_t wreg = (int64_t)(kFft + rows - 1) * kFft * 2 * tsize;
   const int64_t region = align16(stage > wreg ? stage : wreg);
@@ -78,14 +92,16 @@ __host__ __device__ inline LdsLayout lds_layout(int M, int N, int K, int waves, 
   L.tw64 = align16(L.hist_u + (int64_t)K * 4);
   L.twt = L.tw64 + kFft * 2 * 8;
   L.slots = align16(L.twt + kFft * 2 * tsize);
-  L.misc = L.slots + 2LL * waves * 32;
+  L.cand = L.slots + 2LL * waves * 32;
+  L.misc = L.cand + 2LL * waves * 32;
+  L.misc = align16(L.misc);
   L.total = L.misc + 32;
   return L;
 }
 
 template <typename T>
-inline int64_t lds_bytes(int M, int N, int K, int waves) {
-  return lds_layout(M, N, K, waves, (int)sizeof(T)).total;
+inline int64_t lds_bytes(int M, int N, int K, int waves, bool stage_needed = true) {
+  return lds_layout(M, N, K, waves, (int)sizeof(T), stage_needed).total;
 }
 
 }  // namespace fse

@@ -41,7 +41,8 @@ struct fse_plan_s {
   bool own_stream = false;
   std::vector<double> radial;  // M*N, rho^dist (Eq. (2))
   std::vector<double> twid;    // 64 x (cos, sin)(2 pi t / 64)
-  fse::DevBuf tbl_radial, tbl_twid, tbl_twid64;
+  fse::DevBuf tbl_radial, tbl_twid, tbl_twid64, tbl_radial64;
+  fse::DevBuf spec64;          // FP64 spectra of a step (re-rank mode)
   fse::DevBuf work, state, frames_dev, items_dev, u8_img, u8_lost, u8_out, fout, staging,
       trace_u, trace_dc, flags_dev, io_dev;
   std::vector<hipEvent_t> events;

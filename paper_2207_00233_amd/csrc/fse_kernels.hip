@@ -107,51 +107,36 @@ __device__ __forceinline__ unsigned pack_key(unsigned bits, unsigned low) {
 
 // Argmax slot exchanged between wavefronts (32 bytes).
 struct Slot {
-  double e;     // FP64 path: exact |R|^2 of the wave's best entry
+  double e;     // FP64 path: exact |R|^2 of the wave's best entry; re-rank: near-tie count
   double re, im;
   unsigned key; // FP32 path: packed selection key of the wave's best entry
   int k;        // its spectrum index k1 * 64 + k2
 };
 
-template <typename T, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void fse_block_kernel(BlockArgs<T> a) {
+// Phases A-C: gather and weight the area, transform, unpack.  Computes in T,
+// reads the working image in TI.  Returns W0 = sum of weights; when W0 > 0,
+// rr/ri hold X[k] and wvr/wvi hold W[k] for k1 = ROWS wave + j, k2 = lane.
+// Ends with a barrier, after which the LDS region may be reused.
+template <typename T, typename TI, int WAVES>
+__device__ __forceinline__ T forward_transforms(unsigned char* smem, const LdsLayout& L, int M,
+                                                int N, const T* radial, T delta, T zscale,
+                                                const TI* img, const uint8_t* st, int H, int W,
+                                                int oy, int ox, int lane, int wave,
+                                                VecR<T, kFft / WAVES>& rr,
+                                                VecR<T, kFft / WAVES>& ri,
+                                                T (&wvr)[kFft / WAVES], T (&wvi)[kFft / WAVES]) {
   constexpr int THREADS = 64 * WAVES;
   constexpr int ROWS = kFft / WAVES;
   constexpr int QB = (kHalf + WAVES - 1) / WAVES;  // row-DFT columns per wavefront
-  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = uniform_int(tid >> 6);
-  const int M = a.M, N = a.N, NP = N | 1, K = a.K;
-
-  const LdsLayout L = lds_layout(M, N, K, WAVES, (int)sizeof(T));
+  const int NP = N | 1;
   T* xs = reinterpret_cast<T*>(smem);
   T* ws = xs + M * NP;
   T* bx = reinterpret_cast<T*>(smem + L.bx);
   T* bw = reinterpret_cast<T*>(smem + L.bw);
-  T* Wl = reinterpret_cast<T*>(smem);  // (64 + ROWS - 1) x 64 complex, after phase C
-  T* hdc = reinterpret_cast<T*>(smem + L.hist_dc);
-  int* hu = reinterpret_cast<int*>(smem + L.hist_u);
-  double* tw = reinterpret_cast<double*>(smem + L.tw64);
+  T* Zl = reinterpret_cast<T*>(smem);  // 64 x 64 complex, after phase B
   T* twt = reinterpret_cast<T*>(smem + L.twt);
   Slot* slots = reinterpret_cast<Slot*>(smem + L.slots);
-
-  const int item = blockIdx.x;
-  const int fr = a.items[2 * item];
-  const int bij = a.items[2 * item + 1];
-  const int bi = bij >> 16, bj = bij & 0xffff;
-  const FrameDesc fd = a.frames[fr];
-  const int H = fd.H, W = fd.W;
-  T* img = a.work + fd.off;
-  uint8_t* st = a.state + fd.off;
-  const int by0 = bi * a.Bh - a.goy, bx0 = bj * a.Bw - a.gox;
-  const int oy = by0 - a.d, ox = bx0 - a.d;
-
-  if (tid < 2 * kFft) {
-    const double v = a.twid64[tid];
-    tw[tid] = v;
-    twt[tid] = (T)v;
-  }
 
   // ---- A: gather, classify, weight (Eq. (2)) ----
   T wsum = T(0);
@@ -162,9 +147,9 @@ __global__ __launch_bounds__(64 * WAVES) void fse_block_kernel(BlockArgs<T> a) {
     if (y >= 0 && y < H && x >= 0 && x < W) {
       const int64_t p = (int64_t)y * W + x;
       const uint8_t s = st[p];
-      const T fac = s == kKnown ? T(1) : (s == kRecon ? a.delta : T(0));
-      wv = a.radial[i] * fac;
-      xv = img[p] * wv;
+      const T fac = s == kKnown ? T(1) : (s == kRecon ? delta : T(0));
+      wv = radial[i] * fac;
+      xv = (T)img[p] * wv;
     }
     ws[m * NP + n] = wv;
     xs[m * NP + n] = xv;
@@ -176,54 +161,99 @@ __global__ __launch_bounds__(64 * WAVES) void fse_block_kernel(BlockArgs<T> a) {
   T W0 = T(0);
 #pragma unroll
   for (int q = 0; q < WAVES; ++q) W0 += (T)slots[q].e;
+  if (!(W0 > T(0))) return W0;
 
-  if (W0 > T(0)) {
-    // ---- B: real row DFTs, columns k2 = wave + WAVES q, k2 <= 32 ----
-    {
-      T axr[QB], axi[QB], awr[QB], awi[QB];
+  // ---- B: real row DFTs, columns k2 = wave + WAVES q, k2 <= 32 ----
+  {
+    T axr[QB], axi[QB], awr[QB], awi[QB];
 #pragma unroll
-      for (int q = 0; q < QB; ++q) axr[q] = axi[q] = awr[q] = awi[q] = T(0);
-      if (lane < M) {
-        for (int n = 0; n < N; ++n) {
-          const T xv = xs[lane * NP + n], wv = ws[lane * NP + n];
-#pragma unroll
-          for (int q = 0; q < QB; ++q) {
-            const int t = ((wave + WAVES * q) * n) & (kFft - 1);
-            const T c = twt[2 * t], s = twt[2 * t + 1];
-            axr[q] = fma(xv, c, axr[q]);
-            axi[q] = fma(-xv, s, axi[q]);
-            awr[q] = fma(wv, c, awr[q]);
-            awi[q] = fma(-wv, s, awi[q]);
-          }
-        }
+    for (int q = 0; q < QB; ++q) axr[q] = axi[q] = awr[q] = awi[q] = T(0);
+    if (lane < M) {
+      for (int n = 0; n < N; ++n) {
+        const T xv = xs[lane * NP + n], wv = ws[lane * NP + n];
 #pragma unroll
         for (int q = 0; q < QB; ++q) {
-          const int k2 = wave + WAVES * q;
-          if (k2 < kHalf) {
-            T* px = bx + (lane * kHalf + k2) * 2;
-            T* pw = bw + (lane * kHalf + k2) * 2;
-            px[0] = axr[q];
-            px[1] = axi[q];
-            pw[0] = awr[q];
-            pw[1] = awi[q];
-          }
+          const int t = ((wave + WAVES * q) * n) & (kFft - 1);
+          const T c = twt[2 * t], s = twt[2 * t + 1];
+          axr[q] = fma(xv, c, axr[q]);
+          axi[q] = fma(-xv, s, axi[q]);
+          awr[q] = fma(wv, c, awr[q]);
+          awi[q] = fma(-wv, s, awi[q]);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < QB; ++q) {
+        const int k2 = wave + WAVES * q;
+        if (k2 < kHalf) {
+          T* px = bx + (lane * kHalf + k2) * 2;
+          T* pw = bw + (lane * kHalf + k2) * 2;
+          px[0] = axr[q];
+          px[1] = axi[q];
+          pw[0] = awr[q];
+          pw[1] = awi[q];
         }
       }
     }
-    __syncthreads();
+  }
+  __syncthreads();
 
-    // ---- C: column DFT of z = x + j s w for k1 = ROWS wave + j, k2 = lane ----
-    VecR<T, ROWS> rr, ri;
-    {
-      const int c = lane <= 32 ? lane : kFft - lane;
-      const T sg = lane <= 32 ? T(1) : T(-1);  // conjugate mirrored columns
-      const T zs = a.zscale;
+  // ---- C: column DFT of z = x + j s w for k1 = ROWS wave + j, k2 = lane ----
+  {
+    const int c = lane <= 32 ? lane : kFft - lane;
+    const T sg = lane <= 32 ? T(1) : T(-1);  // conjugate mirrored columns
+    auto zval = [&](int m, T& zr, T& zi) {
+      const T xr = bx[(m * kHalf + c) * 2], xi = sg * bx[(m * kHalf + c) * 2 + 1];
+      const T wr = bw[(m * kHalf + c) * 2], wi = sg * bw[(m * kHalf + c) * 2 + 1];
+      zr = fma(-zscale, wi, xr);
+      zi = fma(zscale, wr, xi);
+    };
 #pragma unroll
-      for (int j = 0; j < ROWS; ++j) rr[j] = ri[j] = T(0);
+    for (int j = 0; j < ROWS; ++j) rr[j] = ri[j] = T(0);
+    if constexpr (WAVES == 4) {
+      // 64 = 4 x 16: with m = m0 + 4 m1 and k1 = j + 16 w,
+      //   Z[k1] = sum_m0 e^{-j2pi m0 k1/64} Y_m0[j],
+      //   Y_m0[j] = sum_m1 z[m0 + 4 m1] e^{-j2pi m1 j/16};
+      // wavefront w computes Y_w (16 points) and the four are shared in LDS.
+      for (int m = wave; m < M; m += 4) {
+        T zr, zi;
+        zval(m, zr, zi);
+        const int m1 = m >> 2;
+#pragma unroll
+        for (int j = 0; j < ROWS; ++j) {
+          const int t = (4 * m1 * j) & (kFft - 1);
+          const T cc = twt[2 * t], ss = twt[2 * t + 1];
+          rr[j] = fma(zr, cc, fma(zi, ss, rr[j]));
+          ri[j] = fma(zi, cc, fma(-zr, ss, ri[j]));
+        }
+      }
+      __syncthreads();  // every wavefront is done with the phase-B rows
+#pragma unroll
+      for (int j = 0; j < ROWS; ++j) {
+        T* p = Zl + ((wave * ROWS + j) * kFft + lane) * 2;
+        p[0] = rr[j];
+        p[1] = ri[j];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < ROWS; ++j) {
+        const int k1 = ROWS * wave + j;
+        T ar = T(0), ai = T(0);
+#pragma unroll
+        for (int m0 = 0; m0 < 4; ++m0) {
+          const T* p = Zl + ((m0 * ROWS + j) * kFft + lane) * 2;
+          const T yr = p[0], yi = p[1];
+          const int t = (m0 * k1) & (kFft - 1);
+          const T cc = twt[2 * t], ss = twt[2 * t + 1];
+          ar = fma(yr, cc, fma(yi, ss, ar));
+          ai = fma(yi, cc, fma(-yr, ss, ai));
+        }
+        rr[j] = ar;
+        ri[j] = ai;
+      }
+    } else {
       for (int m = 0; m < M; ++m) {
-        const T xr = bx[(m * kHalf + c) * 2], xi = sg * bx[(m * kHalf + c) * 2 + 1];
-        const T wr = bw[(m * kHalf + c) * 2], wi = sg * bw[(m * kHalf + c) * 2 + 1];
-        const T zr = fma(-zs, wi, xr), zi = fma(zs, wr, xi);
+        T zr, zi;
+        zval(m, zr, zi);
 #pragma unroll
         for (int j = 0; j < ROWS; ++j) {
           const int t = ((ROWS * wave + j) * m) & (kFft - 1);
@@ -233,31 +263,141 @@ __global__ __launch_bounds__(64 * WAVES) void fse_block_kernel(BlockArgs<T> a) {
         }
       }
     }
-    __syncthreads();  // phase-B buffers are dead from here on
+  }
+  __syncthreads();  // phase-B buffers (and the partial DFTs) are dead from here on
+#pragma unroll
+  for (int j = 0; j < ROWS; ++j) {
+    T* p = Zl + ((ROWS * wave + j) * kFft + lane) * 2;
+    p[0] = rr[j];
+    p[1] = ri[j];
+  }
+  __syncthreads();
+  // unpack: X[k] = (Z[k] + conj Z[-k]) / 2, W[k] = (Z[k] - conj Z[-k]) / (2 j s)
+  {
+    const T h = T(0.5), hs = T(0.5) / zscale;
 #pragma unroll
     for (int j = 0; j < ROWS; ++j) {
-      T* p = Wl + ((ROWS * wave + j) * kFft + lane) * 2;
-      p[0] = rr[j];
-      p[1] = ri[j];
+      const int k1 = ROWS * wave + j;
+      const T* p = Zl + ((((kFft - k1) & (kFft - 1)) * kFft) + ((kFft - lane) & (kFft - 1))) * 2;
+      const T pr = p[0], pi = p[1];
+      const T ar = rr[j], ai = ri[j];
+      rr[j] = h * (ar + pr);
+      ri[j] = h * (ai - pi);
+      wvr[j] = hs * (ai + pi);
+      wvi[j] = hs * (pr - ar);
     }
-    __syncthreads();
-    // unpack: X[k] = (Z[k] + conj Z[-k]) / 2, W[k] = (Z[k] - conj Z[-k]) / (2 j s)
-    T wvr[ROWS], wvi[ROWS];
-    {
-      const T h = T(0.5), hs = T(0.5) / a.zscale;
+  }
+  __syncthreads();
+  return W0;
+}
+
+// Twiddle tables into LDS (double for the synthesis, T for the transforms).
+template <typename T>
+__device__ __forceinline__ void load_twiddles(unsigned char* smem, const LdsLayout& L,
+                                              const double* twid64) {
+  const int tid = threadIdx.x;
+  if (tid < 2 * kFft) {
+    const double v = twid64[tid];
+    reinterpret_cast<double*>(smem + L.tw64)[tid] = v;
+    reinterpret_cast<T*>(smem + L.twt)[tid] = (T)v;
+  }
+}
+
+// FP64 transform pass of the re-rank mode: writes R0, W and W0 of every work
+// item in double to BlockArgs::spec64 (the iteration kernel runs in float).
+template <int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void fse_dft64_kernel(BlockArgs<float> a,
+                                                               const double* radial64) {
+  constexpr int ROWS = kFft / WAVES;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = uniform_int(tid >> 6);
+  const LdsLayout L = lds_layout(a.M, a.N, a.K, WAVES, (int)sizeof(double));
+  const int item = blockIdx.x;
+  const int fr = a.items[2 * item], bij = a.items[2 * item + 1];
+  const int bi = bij >> 16, bj = bij & 0xffff;
+  const FrameDesc fd = a.frames[fr];
+  const int by0 = bi * a.Bh - a.goy, bx0 = bj * a.Bw - a.gox;
+  load_twiddles<double>(smem, L, a.twid64);
+  VecR<double, ROWS> rr, ri;
+  double wvr[ROWS], wvi[ROWS];
+  const double W0 = forward_transforms<double, float, WAVES>(
+      smem, L, a.M, a.N, radial64, a.delta64, 128.0, a.work + fd.off, a.state + fd.off,
+      fd.H, fd.W, by0 - a.d, bx0 - a.d, lane, wave, rr, ri, wvr, wvi);
+  double* out = a.spec64 + (int64_t)item * kSpecStride;
+  if (tid == 0) out[kSpecW0] = W0;
+  if (W0 > 0.0) {
+#pragma unroll
+    for (int j = 0; j < ROWS; ++j) {
+      const int k = (ROWS * wave + j) * kFft + lane;
+      out[kSpecR0 + 2 * k] = rr[j];
+      out[kSpecR0 + 2 * k + 1] = ri[j];
+      out[kSpecW + 2 * k] = wvr[j];
+      out[kSpecW + 2 * k + 1] = wvi[j];
+    }
+  }
+}
+
+// RERANK (T = float only): spectra come from fse_dft64_kernel, and near-tied
+// selections are re-scored exactly in double.
+template <typename T, int WAVES, bool RERANK>
+__global__ __launch_bounds__(64 * WAVES) void fse_block_kernel(BlockArgs<T> a) {
+  constexpr int THREADS = 64 * WAVES;
+  constexpr int ROWS = kFft / WAVES;
+  static_assert(!RERANK || sizeof(T) == 4, "re-rank mode iterates in float");
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = uniform_int(tid >> 6);
+  const int K = a.K;
+
+  const LdsLayout L = lds_layout(a.M, a.N, K, WAVES, (int)sizeof(T), !RERANK);
+  T* Wl = reinterpret_cast<T*>(smem);  // (64 + ROWS - 1) x 64 complex
+  T* hdc = reinterpret_cast<T*>(smem + L.hist_dc);
+  int* hu = reinterpret_cast<int*>(smem + L.hist_u);
+  double* tw = reinterpret_cast<double*>(smem + L.tw64);
+  Slot* slots = reinterpret_cast<Slot*>(smem + L.slots);
+
+  const int item = blockIdx.x;
+  const int fr = a.items[2 * item];
+  const int bij = a.items[2 * item + 1];
+  const int bi = bij >> 16, bj = bij & 0xffff;
+  const FrameDesc fd = a.frames[fr];
+  const int H = fd.H, W = fd.W;
+  T* img = a.work + fd.off;
+  uint8_t* st = a.state + fd.off;
+  const int by0 = bi * a.Bh - a.goy, bx0 = bj * a.Bw - a.gox;
+
+  load_twiddles<T>(smem, L, a.twid64);
+
+  VecR<T, ROWS> rr, ri;
+  T wvr[ROWS], wvi[ROWS];
+  T W0;
+  double W0d = 0.0;
+  const double* spec = nullptr;
+  if constexpr (RERANK) {
+    spec = a.spec64 + (int64_t)item * kSpecStride;
+    W0d = spec[kSpecW0];
+    W0 = (T)W0d;
+    if (W0d > 0.0) {
 #pragma unroll
       for (int j = 0; j < ROWS; ++j) {
-        const int k1 = ROWS * wave + j;
-        const T* p = Wl + ((((kFft - k1) & (kFft - 1)) * kFft) + ((kFft - lane) & (kFft - 1))) * 2;
-        const T pr = p[0], pi = p[1];
-        const T ar = rr[j], ai = ri[j];
-        rr[j] = h * (ar + pr);
-        ri[j] = h * (ai - pi);
-        wvr[j] = hs * (ai + pi);
-        wvi[j] = hs * (pr - ar);
+        const int k = (ROWS * wave + j) * kFft + lane;
+        rr[j] = (T)spec[kSpecR0 + 2 * k];
+        ri[j] = (T)spec[kSpecR0 + 2 * k + 1];
+        wvr[j] = (T)spec[kSpecW + 2 * k];
+        wvi[j] = (T)spec[kSpecW + 2 * k + 1];
       }
     }
-    __syncthreads();
+    __syncthreads();  // twiddles visible
+  } else {
+    W0 = forward_transforms<T, T, WAVES>(smem, L, a.M, a.N, a.radial, a.delta, a.zscale, img, st,
+                                         H, W, by0 - a.d, bx0 - a.d, lane, wave, rr, ri, wvr,
+                                         wvi);
+  }
+
+  if (W0 > T(0)) {
 #pragma unroll
     for (int j = 0; j < ROWS; ++j) {
       const int row = ROWS * wave + j;
@@ -281,6 +421,9 @@ __global__ __launch_bounds__(64 * WAVES) void fse_block_kernel(BlockArgs<T> a) {
     //        63 - k1 (a relative resolution of 2^-17, below the rounding
     //        drift of a float spectrum), so one unsigned max gives value and
     //        row; ties go to the smallest k1, then the smallest k2.
+    //  RERANK: when another entry comes within the relative gap of the
+    //        maximum, the candidates are re-scored exactly in double from
+    //        R0 - sum_i dc_i W[k - u_i] and the best exact one is taken.
     const T gs = a.gamma / W0;
     int u = 0;
     T dcr = T(0), dci = T(0);
@@ -317,23 +460,138 @@ __global__ __launch_bounds__(64 * WAVES) void fse_block_kernel(BlockArgs<T> a) {
         const int jw = uniform_int(63 - (int)(wk & 63u) - ROWS * wave);
         const T sr = read_lane((T)rr[jw], lw);
         const T si = read_lane((T)ri[jw], lw);
+        int near = 0;
+        if constexpr (RERANK) {
+          // entries within the gap of this wavefront's maximum (conservative:
+          // the block maximum is at least as large)
+          const float lim = __uint_as_float(wk) * (float)(1.0 - a.rerank_gap);
+          const unsigned thr = __float_as_uint(lim);
+#pragma unroll
+          for (int j = 0; j < ROWS; ++j) near += __builtin_popcountll(__ballot(key[j] >= thr));
+        }
         if (lane == 0) {
           Slot v;
           v.key = wk;
           v.k = ((ROWS * wave + jw) << 6) | lw;
           v.re = sr;
           v.im = si;
+          v.e = (double)near;
           sl[wave] = v;
         }
         __syncthreads();
         // the winning wavefront: largest key (its row is in the key)
-        unsigned gk = lane < WAVES ? sl[lane].key : 0u;
-        gk = wave_max(gk);
+        const unsigned mykey = lane < WAVES ? sl[lane].key : 0u;
+        const unsigned gk = wave_max(mykey);
         const int wwin = uniform_int((63 - (int)(gk & 63u)) / ROWS);
         const Slot best = sl[wwin];
         u = uniform_int(best.k);
         dcr = gs * (T)best.re;
         dci = gs * (T)best.im;
+        if constexpr (RERANK) {
+          const unsigned thr_g = __float_as_uint(__uint_as_float(gk) * (float)(1.0 - a.rerank_gap));
+          const int contrib = (lane < WAVES && mykey >= thr_g) ? (int)sl[lane].e : 0;
+          const bool rerank = __ballot(contrib >= 2) != 0ull ||
+                              __builtin_popcountll(__ballot(contrib >= 1)) >= 2;
+          if (rerank) {  // uniform: every wavefront read the same slots
+            // Every wavefront re-scores its own entries within the gap of the
+            // block maximum (at most kCandWave, in row-major order) exactly in
+            // double, and offers its best one; one barrier joins them.
+            constexpr int kCandWave = 3;
+            unsigned long long packed = 0ull;  // 12-bit indices
+            int nc = 0;
+#pragma unroll
+            for (int j = 0; j < ROWS; ++j) {
+              unsigned long long mm = __ballot(key[j] >= thr_g);
+              while (mm && nc < kCandWave) {
+                const int l = __builtin_ctzll(mm);
+                mm &= mm - 1;
+                packed |= (unsigned long long)(((ROWS * wave + j) << 6) | l) << (12 * nc);
+                ++nc;
+              }
+            }
+            double accr[kCandWave], acci[kCandWave], r0r[kCandWave], r0i[kCandWave];
+#pragma unroll
+            for (int c = 0; c < kCandWave; ++c) {
+              accr[c] = acci[c] = r0r[c] = r0i[c] = 0.0;
+              if (c < nc) {
+                const int kc = (int)((packed >> (12 * c)) & 0xfffull);
+                r0r[c] = spec[kSpecR0 + 2 * kc];
+                r0i[c] = spec[kSpecR0 + 2 * kc + 1];
+              }
+            }
+            // history terms in rounds of 4 x 64 so that all gathers of a
+            // round are in flight together (one memory latency per round)
+            for (int i0 = 0; i0 < it; i0 += 256) {
+              double wr[4][kCandWave], wi[4][kCandWave];
+              int valid[4];
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const int i = i0 + 64 * q + lane;
+                valid[q] = i < it;
+                const int uu = valid[q] ? hu[i] : 0;
+#pragma unroll
+                for (int c = 0; c < kCandWave; ++c) {
+                  wr[q][c] = wi[q][c] = 0.0;
+                  if (c < nc && valid[q]) {
+                    const int kc = (int)((packed >> (12 * c)) & 0xfffull);
+                    const int d1 = ((kc >> 6) - (uu >> 6)) & (kFft - 1);
+                    const int d2 = ((kc & (kFft - 1)) - (uu & (kFft - 1))) & (kFft - 1);
+                    wr[q][c] = spec[kSpecW + 2 * (d1 * kFft + d2)];
+                    wi[q][c] = spec[kSpecW + 2 * (d1 * kFft + d2) + 1];
+                  }
+                }
+              }
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const int i = i0 + 64 * q + lane;
+                const double xr = valid[q] ? (double)hdc[2 * i] : 0.0;
+                const double xi = valid[q] ? (double)hdc[2 * i + 1] : 0.0;
+#pragma unroll
+                for (int c = 0; c < kCandWave; ++c) {
+                  accr[c] = fma(xr, wr[q][c], fma(-xi, wi[q][c], accr[c]));
+                  acci[c] = fma(xr, wi[q][c], fma(xi, wr[q][c], acci[c]));
+                }
+              }
+            }
+            double bex = -1.0, bre = 0.0, bim = 0.0;
+            int bkx = 1 << 30;
+#pragma unroll
+            for (int c = 0; c < kCandWave; ++c) {
+              if (c < nc) {
+                const int kc = (int)((packed >> (12 * c)) & 0xfffull);
+                const double vr = r0r[c] - wave_sum(accr[c]);
+                const double vi = r0i[c] - wave_sum(acci[c]);
+                const double ve = vr * vr + vi * vi;
+                if (ve > bex || (ve == bex && kc < bkx)) {
+                  bex = ve;
+                  bre = vr;
+                  bim = vi;
+                  bkx = kc;
+                }
+              }
+            }
+            Slot* ex = reinterpret_cast<Slot*>(smem + L.cand) + (it & 1) * WAVES;
+            if (lane == 0) {
+              Slot v;
+              v.e = bex;
+              v.re = bre;
+              v.im = bim;
+              v.k = bkx;
+              v.key = 0u;
+              ex[wave] = v;
+            }
+            __syncthreads();
+            Slot bb = ex[0];
+#pragma unroll
+            for (int q = 1; q < WAVES; ++q) {
+              const Slot c = ex[q];
+              if (c.e > bb.e || (c.e == bb.e && c.k < bb.k)) bb = c;
+            }
+            u = uniform_int(bb.k);
+            dcr = (T)(a.gamma64 * bb.re / W0d);
+            dci = (T)(a.gamma64 * bb.im / W0d);
+          }
+        }
       } else {
         T lm = e[0];
 #pragma unroll
@@ -486,28 +744,70 @@ __global__ void fse_finalize_kernel(const IoDesc* io, const uint8_t* state, cons
 
 // ---------------------------------------------------------------- launchers
 
-template <typename T, int WAVES>
-static hipError_t launch_block_w(const BlockArgs<T>& a, int n_items, size_t lds, hipStream_t s) {
-  static size_t attr_bytes = 0;  // largest dynamic LDS size enabled so far
+template <typename K, typename... Args>
+static hipError_t launch_with_lds(K kernel, size_t& attr_bytes, int n_items, int threads,
+                                  size_t lds, hipStream_t s, Args... args) {
   if (lds > attr_bytes) {
-    hipError_t e = hipFuncSetAttribute((const void*)fse_block_kernel<T, WAVES>,
+    hipError_t e = hipFuncSetAttribute((const void*)kernel,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     attr_bytes = lds;
   }
-  hipLaunchKernelGGL((fse_block_kernel<T, WAVES>), dim3(n_items), dim3(64 * WAVES), lds, s, a);
+  hipLaunchKernelGGL(kernel, dim3(n_items), dim3(threads), lds, s, args...);
   return hipGetLastError();
 }
 
+template <typename T, int WAVES, bool RERANK>
+static hipError_t launch_block_w(const BlockArgs<T>& a, int n_items, hipStream_t s) {
+  static size_t attr_bytes = 0;  // largest dynamic LDS size enabled so far
+  const size_t lds = (size_t)lds_bytes<T>(a.M, a.N, a.K, WAVES, !RERANK);
+  return launch_with_lds(fse_block_kernel<T, WAVES, RERANK>, attr_bytes, n_items, 64 * WAVES,
+                         lds, s, a);
+}
+
+// mode: 0 = plain, 1 = FP32 iterations on FP64 spectra with re-ranking
 template <typename T>
-hipError_t launch_block(const BlockArgs<T>& a, int n_items, int waves, hipStream_t s) {
+hipError_t launch_block(const BlockArgs<T>& a, int n_items, int waves, hipStream_t s,
+                        int mode = 0);
+
+template <>
+hipError_t launch_block<double>(const BlockArgs<double>& a, int n_items, int waves, hipStream_t s,
+                                int mode) {
   if (n_items <= 0) return hipSuccess;
-  const size_t lds = (size_t)lds_bytes<T>(a.M, a.N, a.K, waves);
+  if (mode != 0) return hipErrorInvalidValue;
   switch (waves) {
-    case 4: return launch_block_w<T, 4>(a, n_items, lds, s);
-    case 16: return launch_block_w<T, 16>(a, n_items, lds, s);
+    case 4: return launch_block_w<double, 4, false>(a, n_items, s);
+    case 16: return launch_block_w<double, 16, false>(a, n_items, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <>
+hipError_t launch_block<float>(const BlockArgs<float>& a, int n_items, int waves, hipStream_t s,
+                               int mode) {
+  if (n_items <= 0) return hipSuccess;
+  if (mode == 1) {
+    switch (waves) {
+      case 4: return launch_block_w<float, 4, true>(a, n_items, s);
+      case 16: return launch_block_w<float, 16, true>(a, n_items, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (waves) {
+    case 4: return launch_block_w<float, 4, false>(a, n_items, s);
+    case 16: return launch_block_w<float, 16, false>(a, n_items, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// FP64 transform pass of the re-rank mode (one workgroup of 4 wavefronts
+// per work item).
+hipError_t launch_dft64(const BlockArgs<float>& a, const double* radial64, int n_items,
+                        hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  static size_t attr_bytes = 0;
+  const size_t lds = (size_t)lds_bytes<double>(a.M, a.N, a.K, 4, true);
+  return launch_with_lds(fse_dft64_kernel<4>, attr_bytes, n_items, 256, lds, s, a, radial64);
 }
 
 template <typename T>
@@ -543,8 +843,6 @@ hipError_t launch_finalize(const IoDesc* io, int nframes, int64_t max_pixels,
   return hipGetLastError();
 }
 
-template hipError_t launch_block<float>(const BlockArgs<float>&, int, int, hipStream_t);
-template hipError_t launch_block<double>(const BlockArgs<double>&, int, int, hipStream_t);
 template hipError_t launch_scatter<float>(float*, uint8_t*, const FrameDesc*, const int32_t*, int,
                                           const float*, int, int, int, int, hipStream_t);
 template hipError_t launch_scatter<double>(double*, uint8_t*, const FrameDesc*, const int32_t*,

@@ -16,6 +16,7 @@
 #include <cstring>
 #include <mutex>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "fse.h"
@@ -26,7 +27,9 @@
 namespace fse {
 
 template <typename T>
-hipError_t launch_block(const BlockArgs<T>& a, int n_items, int waves, hipStream_t s);
+hipError_t launch_block(const BlockArgs<T>& a, int n_items, int waves, hipStream_t s, int mode);
+hipError_t launch_dft64(const BlockArgs<float>& a, const double* radial64, int n_items,
+                        hipStream_t s);
 template <typename T>
 hipError_t launch_scatter(T* work, uint8_t* state, const FrameDesc* frames, const int32_t* items,
                           int n_items, const T* staging, int Bh, int Bw, int gox, int goy,
@@ -90,7 +93,9 @@ int validate_params(const fse_params* p) {
   if (!(p->gamma > 0.0 && p->gamma <= 1.0)) return FSE_ERR_INVALID;
   if (p->iterations < 1 || p->iterations > FSE_MAX_ITERATIONS) return FSE_ERR_INVALID;
   if (p->order != FSE_ORDER_OPTIMIZED && p->order != FSE_ORDER_LINESCAN) return FSE_ERR_INVALID;
-  if (p->precision != FSE_FP64 && p->precision != FSE_FP32) return FSE_ERR_INVALID;
+  if (p->precision != FSE_FP64 && p->precision != FSE_FP32 && p->precision != FSE_FP32_RERANK)
+    return FSE_ERR_INVALID;
+  if (!(p->rerank_gap >= 0.0 && p->rerank_gap < 0.5)) return FSE_ERR_INVALID;
   if (p->grid_off_x < 0 || p->grid_off_x >= p->block_w || p->grid_off_y < 0 ||
       p->grid_off_y >= p->block_h)
     return FSE_ERR_INVALID;
@@ -142,9 +147,12 @@ static void make_tables(fse_plan_s* pl) {
 int plan_device_init(fse_plan_s* pl) {
   const size_t mn = (size_t)pl->M * pl->N;
   if (pl->tbl_radial.reserve(mn * sizeof(double)) || pl->tbl_twid.reserve(2 * kFft * sizeof(double)) ||
-      pl->tbl_twid64.reserve(2 * kFft * sizeof(double)))
+      pl->tbl_twid64.reserve(2 * kFft * sizeof(double)) ||
+      pl->tbl_radial64.reserve(mn * sizeof(double)))
     return FSE_ERR_DEVICE;
-  if (pl->p.precision == FSE_FP32) {
+  if (hipMemcpy(pl->tbl_radial64.ptr, pl->radial.data(), mn * sizeof(double), hipMemcpyHostToDevice))
+    return FSE_ERR_DEVICE;
+  if (pl->p.precision != FSE_FP64) {
     std::vector<float> r(mn), t(2 * kFft);
     for (size_t i = 0; i < mn; ++i) r[i] = (float)pl->radial[i];
     for (int i = 0; i < 2 * kFft; ++i) t[i] = (float)pl->twid[i];
@@ -365,8 +373,20 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
   a.K = K;
   a.delta = (T)p.delta;
   a.gamma = (T)p.gamma;
+  a.delta64 = p.delta;
+  a.gamma64 = p.gamma;
   a.zscale = (T)128.0;
   a.empty_fill = p.empty_fill;
+  a.rerank_gap = p.rerank_gap > 0.0 ? p.rerank_gap : 1e-4;
+  const bool rerank = p.precision == FSE_FP32_RERANK;
+  a.spec64 = nullptr;
+  if (rerank) {
+    int64_t max_step = 0;
+    for (int t = 0; t < max_waves; ++t) max_step = std::max(max_step, wave_start[t + 1] - wave_start[t]);
+    if ((rc = pl->spec64.reserve(std::max<int64_t>(1, max_step) * kSpecStride * sizeof(double))))
+      return rc;
+    a.spec64 = (double*)pl->spec64.ptr;
+  }
 
   while ((int)pl->events.size() < 2 * max_waves) {
     hipEvent_t e;
@@ -381,7 +401,11 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
     a.trace_dc = want_trace ? (T*)pl->trace_dc.ptr + i0 * K * 2 : nullptr;
     if ((rc = chk(hipEventRecord(pl->events[2 * t], s)))) return rc;
     const int waves = cnt <= pl->wide_threshold ? 16 : 4;
-    if ((rc = chk(launch_block<T>(a, (int)cnt, waves, s)))) return rc;
+    if constexpr (std::is_same<T, float>::value) {
+      if (rerank && (rc = chk(launch_dft64(a, (const double*)pl->tbl_radial64.ptr, (int)cnt, s))))
+        return rc;
+    }
+    if ((rc = chk(launch_block<T>(a, (int)cnt, waves, s, rerank ? 1 : 0)))) return rc;
     if ((rc = chk(hipEventRecord(pl->events[2 * t + 1], s)))) return rc;
     if (staged && (rc = chk(launch_scatter<T>(work, state, a.frames, a.items, (int)cnt,
                                               (const T*)pl->staging.ptr, Bh, Bw, gox, goy, s))))
@@ -475,6 +499,9 @@ int32_t fse_plan(const fse_params* p, void* hip_stream, fse_plan_t* out) {
                                                   : lds_bytes<float>(M, N, K, waves);
     if (need > (int64_t)prop.sharedMemPerBlock) return FSE_ERR_UNSUPPORTED;
   }
+  if (p->precision == FSE_FP32_RERANK &&
+      lds_bytes<double>(M, N, K, 4) > (int64_t)prop.sharedMemPerBlock)
+    return FSE_ERR_UNSUPPORTED;
   fse_plan_s* pl = new fse_plan_s();
   pl->p = *p;
   pl->M = M;
@@ -511,7 +538,8 @@ int32_t fse_plan_destroy(fse_plan_t pl) {
   if (pl->stream) (void)hipStreamSynchronize(pl->stream);
   for (hipEvent_t e : pl->events) (void)hipEventDestroy(e);
   pl->events.clear();
-  DevBuf* bufs[] = {&pl->tbl_radial, &pl->tbl_twid, &pl->tbl_twid64, &pl->work, &pl->state,
+  DevBuf* bufs[] = {&pl->tbl_radial, &pl->tbl_twid, &pl->tbl_twid64, &pl->tbl_radial64,
+                    &pl->spec64, &pl->work, &pl->state,
                     &pl->frames_dev, &pl->items_dev, &pl->u8_img, &pl->u8_lost, &pl->u8_out,
                     &pl->fout, &pl->staging, &pl->trace_u, &pl->trace_dc, &pl->flags_dev,
                     &pl->io_dev};

@@ -26,6 +26,7 @@
 #include <map>
 #include <memory>
 #include <thread>
+#include <type_traits>
 #include <unordered_map>
 #include <vector>
 
@@ -36,7 +37,9 @@
 namespace fse {
 
 template <typename T>
-hipError_t launch_block(const BlockArgs<T>& a, int n_items, int waves, hipStream_t s);
+hipError_t launch_block(const BlockArgs<T>& a, int n_items, int waves, hipStream_t s, int mode);
+hipError_t launch_dft64(const BlockArgs<float>& a, const double* radial64, int n_items,
+                        hipStream_t s);
 template <typename T>
 hipError_t launch_scatter(T* work, uint8_t* state, const FrameDesc* frames, const int32_t* items,
                           int n_items, const T* staging, int Bh, int Bw, int gox, int goy,
@@ -178,7 +181,7 @@ struct Serving {
   std::vector<int> free_slots;
   Arena arena;
   PinnedPool pinned;
-  DevBuf d_work, d_state, d_img, d_lost, d_out, d_frames, d_io, d_staging;
+  DevBuf d_work, d_state, d_img, d_lost, d_out, d_frames, d_io, d_staging, d_spec64;
   int64_t elem_bytes = 0;
   struct Step {
     DevBuf items;
@@ -193,6 +196,7 @@ struct Serving {
 };
 
 static int tsize(const fse_plan_s* pl) { return pl->p.precision == FSE_FP64 ? 8 : 4; }
+// (FSE_FP32_RERANK iterates in float: its working image is float.)
 
 int serving_init(fse_plan_s* pl) {
   Serving* sv = new Serving();
@@ -323,10 +327,15 @@ static void worker_loop(Serving* sv) {
   a.K = p.iterations;
   a.delta = (T)p.delta;
   a.gamma = (T)p.gamma;
+  a.delta64 = p.delta;
+  a.gamma64 = p.gamma;
   a.zscale = (T)128.0;
   a.empty_fill = p.empty_fill;
   a.trace_u = nullptr;
   a.trace_dc = nullptr;
+  a.spec64 = nullptr;
+  a.rerank_gap = p.rerank_gap > 0.0 ? p.rerank_gap : 1e-4;
+  const bool rerank = p.precision == FSE_FP32_RERANK;
 
   auto fail_all = [&](int err) {
     std::lock_guard<std::mutex> lk(sv->mu);
@@ -387,8 +396,10 @@ static void worker_loop(Serving* sv) {
     if (n_items > 0) {
       if (stp.host.reserve(n_items * 2 * sizeof(int32_t)) ||
           stp.items.reserve(n_items * 2 * sizeof(int32_t)) ||
-          (staged && sv->d_staging.reserve(n_items * p.block_h * p.block_w * sizeof(T))))
+          (staged && sv->d_staging.reserve(n_items * p.block_h * p.block_w * sizeof(T))) ||
+          (rerank && sv->d_spec64.reserve(n_items * kSpecStride * sizeof(double))))
         return fail_all(FSE_ERR_DEVICE);
+      a.spec64 = rerank ? (double*)sv->d_spec64.ptr : nullptr;
       int32_t* it = (int32_t*)stp.host.ptr;
       int64_t k = 0;
       for (auto& r : sv->active) {
@@ -405,8 +416,14 @@ static void worker_loop(Serving* sv) {
       a.staging = staged ? (T*)sv->d_staging.ptr : nullptr;
       const int waves = n_items <= pl->wide_threshold ? 16 : 4;
       if (hipMemcpyAsync(stp.items.ptr, stp.host.ptr, n_items * 2 * sizeof(int32_t),
-                         hipMemcpyHostToDevice, s) != hipSuccess ||
-          launch_block<T>(a, (int)n_items, waves, s) != hipSuccess)
+                         hipMemcpyHostToDevice, s) != hipSuccess)
+        return fail_all(FSE_ERR_DEVICE);
+      if constexpr (std::is_same<T, float>::value) {
+        if (rerank && launch_dft64(a, (const double*)pl->tbl_radial64.ptr, (int)n_items, s) !=
+                          hipSuccess)
+          return fail_all(FSE_ERR_DEVICE);
+      }
+      if (launch_block<T>(a, (int)n_items, waves, s, rerank ? 1 : 0) != hipSuccess)
         return fail_all(FSE_ERR_DEVICE);
       if (staged && launch_scatter<T>(a.work, a.state, a.frames, a.items, (int)n_items, a.staging,
                                       p.block_h, p.block_w, p.grid_off_x, p.grid_off_y,
@@ -484,7 +501,7 @@ void serving_shutdown(fse_plan_s* pl) {
     st.host.release();
   }
   DevBuf* bufs[] = {&sv->d_work, &sv->d_state, &sv->d_img, &sv->d_lost, &sv->d_out,
-                    &sv->d_frames, &sv->d_io, &sv->d_staging};
+                    &sv->d_frames, &sv->d_io, &sv->d_staging, &sv->d_spec64};
   for (DevBuf* b : bufs) b->release();
   sv->host_desc.release();
   delete sv;

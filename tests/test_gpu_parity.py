@@ -247,3 +247,83 @@ def test_config3_full_batch_sampled_blocks():
           f"max {errs.max():.3e} within 0.5: {np.mean(errs <= FP32_TOL):.3f}", flush=True)
     assert np.median(errs) <= 0.05
     assert np.mean(errs <= FP32_TOL) >= 0.9
+
+
+# ------------------------------------------------------------ FP32 + FP64 re-rank
+
+@pytest.mark.parametrize("seed", [5, 11])
+def test_rerank_teacher_forced_blocks(seed):
+    fr = synth.config2(seed=seed, size=128)
+    p = fse.Params(border_d=14, iterations=200, precision=fse.FSE_FP32_RERANK)
+    r = run_gpu(p, [fr.image], [fr.lost])[0]
+    op = oracle_params(p)
+    _, wave_of, seq = oracle.schedule(
+        fr.lost.reshape(8, 16, 8, 16).any(axis=(1, 3)).astype(np.uint8))
+    worst = 0.0
+    for b in seq:
+        o_v, g_v, _ = teacher_forced_block(fr.image, fr.lost, r.out_f.astype(np.float64),
+                                           wave_of, op, b // 8, b % 8)
+        worst = max(worst, np.abs(o_v - g_v).max())
+    print(f"[parity] FP32+rerank teacher-forced max-abs over {len(seq)} blocks: {worst:.3e}",
+          flush=True)
+    assert worst <= FP32_TOL, worst
+
+
+def test_rerank_free_running_and_batch_identity():
+    rng = np.random.default_rng(22)
+    img = synth.polygon_image(rng, 100, 120, radius=(10, 60))
+    lost = synth.bernoulli_block_loss(rng, 100, 120, 16, 0.35)
+    p = fse.Params(border_d=14, iterations=200, precision=fse.FSE_FP32_RERANK)
+    r, _ = check_free_running(p, img, lost, None, PSNR_GAP)
+    other = synth.polygon_image(rng, 64, 80, radius=(10, 30))
+    olost = synth.slice_loss(rng, 64, 80, 16, (0.2, 0.4))
+    rb = run_gpu(p, [other, img], [olost, lost])[1]
+    np.testing.assert_array_equal(rb.out_f, r.out_f)
+
+
+def test_rerank_index_agreement_with_oracle():
+    fr = synth.config2(seed=6, size=96)
+    p = fse.Params(border_d=14, iterations=200, precision=fse.FSE_FP32_RERANK)
+    r = run_gpu(p, [fr.image], [fr.lost], trace=True)[0]
+    op = oracle_params(p)
+    grid = fr.lost.reshape(6, 16, 6, 16).any(axis=(1, 3)).astype(np.uint8)
+    _, wave_of, seq = oracle.schedule(grid)
+    agrees = []
+    for slot, b in enumerate(r.trace_block):
+        _, _, res = teacher_forced_block(fr.image, fr.lost, r.out_f.astype(np.float64),
+                                         wave_of, op, b // 6, b % 6)
+        agree, _ = index_agreement(res.u, r.trace_u[slot])
+        agrees.append(agree)
+    print(f"[parity] FP32+rerank index agreement: mean {np.mean(agrees):.4f} "
+          f"min {np.min(agrees):.4f}", flush=True)
+    assert np.mean(agrees) >= 0.95
+
+
+def test_config3_full_batch_rerank_sampled_blocks():
+    """The 64-frame batch at K=200 with FP32 iterations and FP64 re-ranking:
+    24 seeded blocks, each fed to the oracle with the exact area it saw, all
+    within 0.5 on the 8-bit scale."""
+    frames = synth.config3(seed=0)
+    p = fse.Params(border_d=14, iterations=200, precision=fse.FSE_FP32_RERANK)
+    res = run_gpu(p, [f.image for f in frames], [f.lost for f in frames])
+    op = oracle_params(p)
+    rng = np.random.default_rng(0)
+    errs = []
+    for fi in rng.choice(len(frames), 12, replace=False):
+        fr, r = frames[fi], res[fi]
+        m = fr.lost.astype(bool)
+        np.testing.assert_array_equal(r.out[~m], fr.image[~m])
+        H, W = fr.image.shape
+        hb, wb = -(-H // 16), -(-W // 16)
+        pad = np.zeros((hb * 16, wb * 16), bool)
+        pad[:H, :W] = m
+        grid = pad.reshape(hb, 16, wb, 16).any(axis=(1, 3)).astype(np.uint8)
+        _, wave_of, seq = oracle.schedule(grid)
+        for b in rng.choice(seq, 2, replace=False):
+            o_v, g_v, _ = teacher_forced_block(fr.image, fr.lost, r.out_f.astype(np.float64),
+                                               wave_of, op, b // wb, b % wb)
+            errs.append(np.abs(o_v - g_v).max())
+    errs = np.array(errs)
+    print(f"[parity] FP32+rerank full-size teacher-forced: median {np.median(errs):.3e} "
+          f"max {errs.max():.3e}", flush=True)
+    assert errs.max() <= FP32_TOL

@@ -25,7 +25,7 @@ def _alone(p, frames):
         return [plan.fse_conceal_image([im], [ls], want_float=True)[0] for im, ls in frames]
 
 
-@pytest.mark.parametrize("precision", [fse.FSE_FP32, fse.FSE_FP64])
+@pytest.mark.parametrize("precision", [fse.FSE_FP32, fse.FSE_FP64, fse.FSE_FP32_RERANK])
 def test_served_results_equal_alone(precision):
     frames = _frames(1, [(96, 128), (45, 70), (128, 96), (64, 64), (80, 112), (33, 47)])
     p = fse.Params(border_d=14, iterations=60, precision=precision)
