@@ -30,9 +30,30 @@ BLOCK = 16
 # update R -= dc * W[k-u] (4 FMA = 8 flop) and |R|^2 (3 flop), 4096 entries;
 # two real 64x64 transforms at FFT cost (2 * 2.5 * 4096 * log2(4096) flop);
 # the synthesis on 16x16 lost samples (4 flop per sample and iteration).
-FLOPS_PER_BLOCK = 11 * 4096 * K_ITER + 2 * 2.5 * 4096 * 12 + 256 * K_ITER * 4
+ITER_FLOPS = 11 * 4096 * K_ITER
+TRANSFORM_FLOPS = 2 * 2.5 * 4096 * 12
+SYNTH_FLOPS = 256 * K_ITER * 4
+FLOPS_PER_BLOCK = ITER_FLOPS + TRANSFORM_FLOPS + SYNTH_FLOPS
 PEAK_FP32_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (non-packed FMA)
 PEAK_FP32_PUBLISHED = 157.3
+
+
+def measured_traffic(precision):
+    """HBM bytes per launch of the block kernel from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE measurement, if it was taken on this kernel source
+    and precision; None otherwise."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "fse_block_kernel_traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for fn in ("paper_2207_00233_amd/csrc/fse_kernels.hip", "paper_2207_00233_amd/csrc/fse_device.h"):
+        h.update(open(os.path.join(ROOT, fn), "rb").read())
+    if rec.get("precision") != precision or rec.get("kernel_source_sha256") != h.hexdigest():
+        return None
+    return rec["traffic_bytes_per_launch"]
 
 
 def log(*a):
@@ -192,19 +213,21 @@ def main():
         for _ in range(warmup):
             plan.conceal_device(descs)
         torch.cuda.synchronize()
-        kms, launches, blocks = 0.0, 0, 0
+        kms, tms, launches, blocks = 0.0, 0.0, 0, 0
         t0 = time.perf_counter()
         for _ in range(steps):
             plan.conceal_device(descs)
             cs = plan.last_call_stats()
             kms += cs["kernel_ms"]
+            tms += cs["transform_ms"]
             launches += cs["launches"]
             blocks += cs["blocks"]
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         plan.close()
         return {"value": blocks / dt, "ms_per_step": dt / steps * 1e3,
-                "kernel_ms_per_step": kms / steps, "launches_per_step": launches // steps,
+                "kernel_ms_per_step": kms / steps, "transform_ms_per_step": tms / steps,
+                "launches_per_step": launches // steps,
                 "blocks_per_step": blocks // steps, "avg_launch_ms": kms / max(1, launches),
                 "blocks_per_launch": blocks / max(1, launches)}
 
@@ -228,7 +251,12 @@ def main():
     launches = head["launches_per_step"] * args.steps
     avg_launch_ms = head["avg_launch_ms"]
     blocks_per_launch = head["blocks_per_launch"]
-    achieved = FLOPS_PER_BLOCK * blocks_per_launch / (avg_launch_ms * 1e-3) / 1e12
+    # the dominant kernel is the per-block iteration kernel; in the re-rank
+    # mode the transforms run in a separate FP64 pass
+    kflops = (ITER_FLOPS + SYNTH_FLOPS if args.precision == "fp32_rerank"
+              else FLOPS_PER_BLOCK)
+    achieved = kflops * blocks_per_launch / (avg_launch_ms * 1e-3) / 1e12
+    traffic = measured_traffic(args.precision)
 
     fp64 = None
     if not args.no_fp64:
@@ -287,11 +315,13 @@ def main():
                    "lost_blocks_per_step": lost_blocks, "frames": len(frames),
                    "launches_per_step": launches // args.steps},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-                     "kernel": "fse_block_kernel<float>" + (" + fse_dft64_kernel"
-                                                            if args.precision == "fp32_rerank" else ""),
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
+                     "kernel": "fse_block_kernel<float>",
                      "avg_launch_ms": avg_launch_ms, "blocks_per_launch": blocks_per_launch,
-                     "flops_per_block": FLOPS_PER_BLOCK,
+                     "flops_per_block": kflops,
+                     "traffic_note": "HBM bytes per launch from rocprofv3 FETCH_SIZE x2.0 + "
+                                     "WRITE_SIZE x1.0 (copy-calibrated), taken on this kernel "
+                                     "source; null when the source changed since",
                      "frac_of_published_fp32_peak": achieved / PEAK_FP32_PUBLISHED},
         "fp64_plain": fp64,
         "precision_sweep": sweep,

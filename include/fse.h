@@ -184,14 +184,17 @@ int32_t fse_poll(fse_plan_t plan, uint64_t ticket, int32_t timeout_us);
 int32_t fse_schedule(int32_t hb, int32_t wb, const uint8_t *lost, int32_t order,
                      int32_t *wave_of, int32_t *seq);
 
-/* Device time of the wave kernels of the last fse_conceal_image call, summed
- * over its launches and measured with HIP events on the plan's stream, and
- * the number of those launches and of the blocks they processed. */
+/* Device time of the per-block iteration kernel of the last
+ * fse_conceal_image call, summed over its launches (one per step) and
+ * measured with HIP events on the plan's stream, the number of those launches
+ * and of the blocks they processed, the device time of the FP64 transform
+ * pass (FSE_FP32_RERANK only) and the host wall time of the call. */
 typedef struct {
   double kernel_ms;
   int64_t launches;
   int64_t blocks;
-  double total_ms;   /* host wall time of the call */
+  double total_ms;
+  double transform_ms;
 } fse_call_stats;
 int32_t fse_last_call_stats(fse_plan_t plan, fse_call_stats *out);
 

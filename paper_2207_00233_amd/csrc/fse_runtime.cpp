@@ -388,7 +388,7 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
     a.spec64 = (double*)pl->spec64.ptr;
   }
 
-  while ((int)pl->events.size() < 2 * max_waves) {
+  while ((int)pl->events.size() < 3 * max_waves) {
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return FSE_ERR_DEVICE;
     pl->events.push_back(e);
@@ -399,14 +399,15 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
     a.staging = staged ? (T*)pl->staging.ptr : nullptr;
     a.trace_u = want_trace ? (int32_t*)pl->trace_u.ptr + i0 * K : nullptr;
     a.trace_dc = want_trace ? (T*)pl->trace_dc.ptr + i0 * K * 2 : nullptr;
-    if ((rc = chk(hipEventRecord(pl->events[2 * t], s)))) return rc;
     const int waves = cnt <= pl->wide_threshold ? 16 : 4;
+    if ((rc = chk(hipEventRecord(pl->events[3 * t], s)))) return rc;
     if constexpr (std::is_same<T, float>::value) {
       if (rerank && (rc = chk(launch_dft64(a, (const double*)pl->tbl_radial64.ptr, (int)cnt, s))))
         return rc;
     }
+    if ((rc = chk(hipEventRecord(pl->events[3 * t + 1], s)))) return rc;
     if ((rc = chk(launch_block<T>(a, (int)cnt, waves, s, rerank ? 1 : 0)))) return rc;
-    if ((rc = chk(hipEventRecord(pl->events[2 * t + 1], s)))) return rc;
+    if ((rc = chk(hipEventRecord(pl->events[3 * t + 2], s)))) return rc;
     if (staged && (rc = chk(launch_scatter<T>(work, state, a.frames, a.items, (int)cnt,
                                               (const T*)pl->staging.ptr, Bh, Bw, gox, goy, s))))
       return rc;
@@ -432,12 +433,15 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
   }
   if ((rc = chk(hipStreamSynchronize(s)))) return rc;
 
-  double kms = 0.0;
+  double kms = 0.0, tms = 0.0;
   for (int t = 0; t < max_waves; ++t) {
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, pl->events[2 * t], pl->events[2 * t + 1]) == hipSuccess) kms += ms;
+    if (hipEventElapsedTime(&ms, pl->events[3 * t + 1], pl->events[3 * t + 2]) == hipSuccess) kms += ms;
+    if (rerank && hipEventElapsedTime(&ms, pl->events[3 * t], pl->events[3 * t + 1]) == hipSuccess)
+      tms += ms;
   }
   pl->last.kernel_ms = kms;
+  pl->last.transform_ms = tms;
   pl->last.launches = max_waves;
   pl->last.blocks = n_items;
 
