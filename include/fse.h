@@ -135,6 +135,10 @@ typedef struct {
  * Errors: FSE_ERR_INVALID (p or out null, parameter out of range,
  * block + 2d > fft), FSE_ERR_UNSUPPORTED (fft other than 64 x 64),
  * FSE_ERR_DEVICE (no usable device).  On error *out is set to NULL.
+ * Tuning: the environment variable FSE_WAVE_THRESHOLDS="t16,t8", read here,
+ * sets the launch sizes (blocks per launch) up to which a block runs on 16
+ * or on 8 wavefronts instead of 4; results equal the oracle's to the same
+ * tolerance in every shape, not bit for bit across shapes.
  */
 int32_t fse_plan(const fse_params *p, void *hip_stream, fse_plan_t *out);
 

@@ -46,7 +46,14 @@ struct fse_plan_s {
   fse::DevBuf work, state, frames_dev, items_dev, u8_img, u8_lost, u8_out, fout, staging,
       trace_u, trace_dc, flags_dev, io_dev;
   std::vector<hipEvent_t> events;
-  int wide_threshold = 256;  // waves with at most this many blocks use 16 wavefronts per block
+  // wavefronts per block by launch size: at most wide_threshold blocks -> 16,
+  // at most mid_threshold -> 8, else 4 (fewer blocks than the GPU holds leave
+  // SIMDs idle; more wavefronts per block shorten each block's iteration)
+  int wide_threshold = 256;
+  int mid_threshold = 0;
+  int waves_for(int64_t n_items) const {
+    return n_items <= wide_threshold ? 16 : (n_items <= mid_threshold ? 8 : 4);
+  }
   bool stagger = true;       // staggered frame starts inside a batch
   // launch cost model used to stagger frames: max(latency, blocks / rate),
   // [0] = FP64, [1] = FP32; measured on MI355X for 16x16 blocks, d = 14, K = 200

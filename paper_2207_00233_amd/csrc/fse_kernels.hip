@@ -19,8 +19,9 @@
 // Spectrum layout in the iteration: wavefront w owns rows k1 = ROWS*w ..
 // ROWS*w + ROWS-1 (ROWS = 64 / WAVES), lane l owns column k2 = l, so every lane
 // keeps ROWS complex entries in registers and reads W[k - u] from LDS with a
-// per-lane column offset.  WAVES = 4 is the throughput shape; WAVES = 16
-// quarters the serial work per iteration for waves too small to fill the GPU.
+// per-lane column offset.  WAVES = 4 is the throughput shape; WAVES = 8 and 16
+// halve and quarter the serial work per iteration for launches too small to
+// fill the GPU.
 #include <hip/hip_runtime.h>
 
 #include "fse_device.h"
@@ -93,6 +94,18 @@ __device__ __forceinline__ V wave_max(V x) {
   }
 }
 
+// Maximum over groups of G adjacent lanes when the data repeat with period G
+// (G = 2, 4, 8 or 16); returned uniform (lane 0's group).
+template <int G>
+__device__ __forceinline__ unsigned group_max(unsigned x) {
+  static_assert(G == 2 || G == 4 || G == 8 || G == 16, "group of 2, 4, 8 or 16 lanes");
+  x = dpp_max_step<0xB1, 0xF>(x);                          // quad_perm [1,0,3,2]
+  if constexpr (G >= 4) x = dpp_max_step<0x4E, 0xF>(x);   // quad_perm [2,3,0,1]
+  if constexpr (G >= 8) x = dpp_max_step<0x124, 0xF>(x);  // row_ror:4
+  if constexpr (G >= 16) x = dpp_max_step<0x128, 0xF>(x); // row_ror:8
+  return (unsigned)__builtin_amdgcn_readfirstlane((int)x);
+}
+
 __device__ __forceinline__ unsigned umax3(unsigned a, unsigned b, unsigned c) {
   return max(a, max(b, c));
 }
@@ -104,6 +117,13 @@ __device__ __forceinline__ unsigned pack_key(unsigned bits, unsigned low) {
   asm("v_bfi_b32 %0, 63, %1, %2" : "=v"(r) : "s"(low), "v"(bits));
   return r;
 }
+
+// Argmax slot of the FP32 iteration (16 bytes): the wavefront's best entry.
+struct FSlot {
+  unsigned key;  // packed selection key
+  int k;         // spectrum index k1 * 64 + k2
+  float re, im;  // residual value
+};
 
 // Argmax slot exchanged between wavefronts (32 bytes).
 struct Slot {
@@ -431,10 +451,19 @@ __global__ __launch_bounds__(64 * WAVES) void fse_block_kernel(BlockArgs<T> a) {
       const int col = (lane - (u & (kFft - 1))) & (kFft - 1);
       const int b = uniform_int((ROWS * wave - (u >> 6)) & (kFft - 1));
       const T* wp = Wl + (b * kFft + col) * 2;
+      // all W reads of the iteration in flight before the first update, so
+      // that one LDS latency is exposed per iteration instead of one per pair
+      T wvr_[ROWS], wvi_[ROWS];
+#pragma unroll
+      for (int j = 0; j < ROWS; ++j) {
+        wvr_[j] = wp[j * kFft * 2];
+        wvi_[j] = wp[j * kFft * 2 + 1];
+      }
+      if constexpr (sizeof(T) == 4) __builtin_amdgcn_sched_barrier(0);
       VecR<T, ROWS> e;
 #pragma unroll
       for (int j = 0; j < ROWS; ++j) {
-        const T wr = wp[j * kFft * 2], wi = wp[j * kFft * 2 + 1];
+        const T wr = wvr_[j], wi = wvi_[j];
         T r = rr[j], q = ri[j];
         r = fma(-dcr, wr, r);
         r = fma(dci, wi, r);
@@ -444,7 +473,6 @@ __global__ __launch_bounds__(64 * WAVES) void fse_block_kernel(BlockArgs<T> a) {
         ri[j] = q;
         e[j] = fma(r, r, q * q);
       }
-      Slot* sl = slots + (it & 1) * WAVES;
       if constexpr (sizeof(T) == 4) {
         unsigned key[ROWS];
 #pragma unroll
@@ -469,27 +497,32 @@ __global__ __launch_bounds__(64 * WAVES) void fse_block_kernel(BlockArgs<T> a) {
 #pragma unroll
           for (int j = 0; j < ROWS; ++j) near += __builtin_popcountll(__ballot(key[j] >= thr));
         }
+        FSlot* fs = reinterpret_cast<FSlot*>(smem + L.slots) + (it & 1) * WAVES;
+        int* nr = reinterpret_cast<int*>(smem + L.slots + 2 * WAVES * sizeof(FSlot)) +
+                  (it & 1) * WAVES;
         if (lane == 0) {
-          Slot v;
+          FSlot v;
           v.key = wk;
           v.k = ((ROWS * wave + jw) << 6) | lw;
           v.re = sr;
           v.im = si;
-          v.e = (double)near;
-          sl[wave] = v;
+          fs[wave] = v;
+          if constexpr (RERANK) nr[wave] = near;
         }
         __syncthreads();
-        // the winning wavefront: largest key (its row is in the key)
-        const unsigned mykey = lane < WAVES ? sl[lane].key : 0u;
-        const unsigned gk = wave_max(mykey);
+        // every lane reads the slot of wavefront lane % WAVES (one LDS round
+        // trip); the winning wavefront has the largest key (its row is in the
+        // key), and its entry is taken from that lane
+        const FSlot mine = fs[lane & (WAVES - 1)];
+        const unsigned gk = group_max<WAVES>(mine.key);
         const int wwin = uniform_int((63 - (int)(gk & 63u)) / ROWS);
-        const Slot best = sl[wwin];
-        u = uniform_int(best.k);
-        dcr = gs * (T)best.re;
-        dci = gs * (T)best.im;
+        u = uniform_int(__builtin_amdgcn_readlane(mine.k, wwin));
+        dcr = gs * read_lane(mine.re, wwin);
+        dci = gs * read_lane(mine.im, wwin);
         if constexpr (RERANK) {
           const unsigned thr_g = __float_as_uint(__uint_as_float(gk) * (float)(1.0 - a.rerank_gap));
-          const int contrib = (lane < WAVES && mykey >= thr_g) ? (int)sl[lane].e : 0;
+          const int contrib =
+              (lane < WAVES && mine.key >= thr_g) ? nr[lane & (WAVES - 1)] : 0;
           const bool rerank = __ballot(contrib >= 2) != 0ull ||
                               __builtin_popcountll(__ballot(contrib >= 1)) >= 2;
           if (rerank) {  // uniform: every wavefront read the same slots
@@ -593,6 +626,7 @@ __global__ __launch_bounds__(64 * WAVES) void fse_block_kernel(BlockArgs<T> a) {
           }
         }
       } else {
+        Slot* sl = slots + (it & 1) * WAVES;
         T lm = e[0];
 #pragma unroll
         for (int j = 1; j < ROWS; ++j) lm = fmax(lm, e[j]);
@@ -777,6 +811,7 @@ hipError_t launch_block<double>(const BlockArgs<double>& a, int n_items, int wav
   if (mode != 0) return hipErrorInvalidValue;
   switch (waves) {
     case 4: return launch_block_w<double, 4, false>(a, n_items, s);
+    case 8: return launch_block_w<double, 8, false>(a, n_items, s);
     case 16: return launch_block_w<double, 16, false>(a, n_items, s);
     default: return hipErrorInvalidValue;
   }
@@ -789,12 +824,14 @@ hipError_t launch_block<float>(const BlockArgs<float>& a, int n_items, int waves
   if (mode == 1) {
     switch (waves) {
       case 4: return launch_block_w<float, 4, true>(a, n_items, s);
+      case 8: return launch_block_w<float, 8, true>(a, n_items, s);
       case 16: return launch_block_w<float, 16, true>(a, n_items, s);
       default: return hipErrorInvalidValue;
     }
   }
   switch (waves) {
     case 4: return launch_block_w<float, 4, false>(a, n_items, s);
+    case 8: return launch_block_w<float, 8, false>(a, n_items, s);
     case 16: return launch_block_w<float, 16, false>(a, n_items, s);
     default: return hipErrorInvalidValue;
   }

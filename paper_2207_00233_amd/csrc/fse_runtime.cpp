@@ -399,7 +399,7 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
     a.staging = staged ? (T*)pl->staging.ptr : nullptr;
     a.trace_u = want_trace ? (int32_t*)pl->trace_u.ptr + i0 * K : nullptr;
     a.trace_dc = want_trace ? (T*)pl->trace_dc.ptr + i0 * K * 2 : nullptr;
-    const int waves = cnt <= pl->wide_threshold ? 16 : 4;
+    const int waves = pl->waves_for(cnt);
     if ((rc = chk(hipEventRecord(pl->events[3 * t], s)))) return rc;
     if constexpr (std::is_same<T, float>::value) {
       if (rerank && (rc = chk(launch_dft64(a, (const double*)pl->tbl_radial64.ptr, (int)cnt, s))))
@@ -498,7 +498,7 @@ int32_t fse_plan(const fse_params* p, void* hip_stream, fse_plan_t* out) {
   if (hipGetDevice(&dev) != hipSuccess) return FSE_ERR_DEVICE;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return FSE_ERR_DEVICE;
-  for (int waves : {4, 16}) {
+  for (int waves : {4, 8, 16}) {
     const int64_t need = p->precision == FSE_FP64 ? lds_bytes<double>(M, N, K, waves)
                                                   : lds_bytes<float>(M, N, K, waves);
     if (need > (int64_t)prop.sharedMemPerBlock) return FSE_ERR_UNSUPPORTED;
@@ -520,6 +520,13 @@ int32_t fse_plan(const fse_params* p, void* hip_stream, fse_plan_t* out) {
       return FSE_ERR_DEVICE;
     }
     pl->own_stream = true;
+  }
+  if (const char* env = std::getenv("FSE_WAVE_THRESHOLDS")) {
+    int t16 = 0, t8 = 0;
+    if (std::sscanf(env, "%d,%d", &t16, &t8) == 2 && t16 >= 0 && t8 >= 0) {
+      pl->wide_threshold = t16;
+      pl->mid_threshold = t8;
+    }
   }
   make_tables(pl);
   rc = plan_device_init(pl);

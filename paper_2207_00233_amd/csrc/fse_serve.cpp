@@ -414,7 +414,7 @@ static void worker_loop(Serving* sv) {
       }
       a.items = (const int32_t*)stp.items.ptr;
       a.staging = staged ? (T*)sv->d_staging.ptr : nullptr;
-      const int waves = n_items <= pl->wide_threshold ? 16 : 4;
+      const int waves = pl->waves_for(n_items);
       if (hipMemcpyAsync(stp.items.ptr, stp.host.ptr, n_items * 2 * sizeof(int32_t),
                          hipMemcpyHostToDevice, s) != hipSuccess)
         return fail_all(FSE_ERR_DEVICE);

@@ -327,3 +327,41 @@ def test_config3_full_batch_rerank_sampled_blocks():
     print(f"[parity] FP32+rerank full-size teacher-forced: median {np.median(errs):.3e} "
           f"max {errs.max():.3e}", flush=True)
     assert errs.max() <= FP32_TOL
+
+
+# ------------------------------------------------------------ launch shapes
+
+SHAPES = {"4 wavefronts": "0,0", "8 wavefronts": "0,1000000", "16 wavefronts": "1000000,0"}
+
+
+@pytest.mark.parametrize("shape", list(SHAPES))
+@pytest.mark.parametrize("precision", [fse.FSE_FP64, fse.FSE_FP32_RERANK, fse.FSE_FP32])
+def test_every_launch_shape_matches_oracle(monkeypatch, shape, precision):
+    """Each workgroup shape (4, 8 or 16 wavefronts per block, forced for every
+    launch) against the oracle: FP64 free-running to 1e-7; the FP32 modes
+    teacher-forced per block (re-rank: every block within 0.5; plain FP32:
+    the statistical bar of its near-tie reading)."""
+    monkeypatch.setenv("FSE_WAVE_THRESHOLDS", SHAPES[shape])
+    if precision == fse.FSE_FP64:
+        rng = np.random.default_rng(21)
+        img = synth.polygon_image(rng, 100, 120, radius=(10, 60))
+        lost = synth.bernoulli_block_loss(rng, 100, 120, 16, 0.35)
+        p = fse.Params(border_d=14, iterations=60, precision=precision)
+        check_free_running(p, img, lost, FP64_TOL)
+        return
+    fr = synth.config2(seed=5, size=128)
+    p = fse.Params(border_d=14, iterations=200, precision=precision)
+    r = run_gpu(p, [fr.image], [fr.lost])[0]
+    op = oracle_params(p)
+    _, wave_of, seq = oracle.schedule(
+        fr.lost.reshape(8, 16, 8, 16).any(axis=(1, 3)).astype(np.uint8))
+    errs = np.array([np.abs(np.subtract(*teacher_forced_block(
+        fr.image, fr.lost, r.out_f.astype(np.float64), wave_of, op, b // 8, b % 8)[:2])).max()
+        for b in seq])
+    print(f"[parity] {shape} precision {precision}: teacher-forced median "
+          f"{np.median(errs):.3e} max {errs.max():.3e} over {len(seq)} blocks", flush=True)
+    if precision == fse.FSE_FP32_RERANK:
+        assert errs.max() <= FP32_TOL
+    else:
+        assert np.median(errs) <= 0.05
+        assert np.mean(errs <= FP32_TOL) >= 0.9
