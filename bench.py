@@ -88,6 +88,77 @@ def cpu_baseline(frames, budget_s=15.0):
                       f"{blocks} lost blocks, {dt:.1f} s, FP64, K={K_ITER}"}
 
 
+def psnr_lost(out, ref, lost):
+    m = lost.astype(bool)
+    mse = np.mean((out[m].astype(np.float64) - ref[m].astype(np.float64)) ** 2)
+    return float(10 * np.log10(255.0 ** 2 / mse)) if mse > 0 else float("inf")
+
+
+def order_frames(synth, seeds=(0, 1, 2)):
+    return [synth.config2(seed=s) for s in seeds]
+
+
+def order_comparison_gpu(fse, frames, precision, reps=3):
+    """512x512 polygon images with 16x16 blocks lost i.i.d. (p = 0.25), the
+    optimized order (Algorithm 1) against the line scan on the GPU: PSNR on the
+    lost samples against the ground truth, number of waves, lost blocks per
+    second and wall time per frame (host buffers, one frame per call)."""
+    res = {}
+    for name, order in (("optimized", fse.FSE_ORDER_OPTIMIZED), ("line_scan", fse.FSE_ORDER_LINESCAN)):
+        p = fse.Params(border_d=BORDER, iterations=K_ITER, precision=precision, order=order)
+        with fse.Plan(p) as plan:
+            psnrs, waves, blocks, times = [], [], 0, []
+            for fr in frames:
+                plan.fse_conceal_image([fr.image], [fr.lost])
+                for _ in range(reps):
+                    t0 = time.perf_counter()
+                    r = plan.fse_conceal_image([fr.image], [fr.lost])[0]
+                    times.append(time.perf_counter() - t0)
+                psnrs.append(psnr_lost(r.out, fr.image, fr.lost))
+                waves.append(r.waves)
+                blocks += r.lost_blocks
+        res[name] = {"psnr_db": psnrs, "mean_psnr_db": float(np.mean(psnrs)), "waves": waves,
+                     "ms_per_frame": float(np.median(times) * 1e3),
+                     "lost_blocks_per_s": blocks / (np.median(times) * len(frames))}
+    res["gain_db"] = res["optimized"]["mean_psnr_db"] - res["line_scan"]["mean_psnr_db"]
+    return res
+
+
+def order_comparison_oracle(frames):
+    """The same comparison computed by the FP64 oracle (all host cores)."""
+    import oracle
+    cores = len(os.sched_getaffinity(0))
+    res = {}
+    for name, order in (("optimized", 0), ("line_scan", 1)):
+        p = oracle.Params(border_d=BORDER, iterations=K_ITER, nthreads=cores, order=order)
+        psnrs, waves = [], []
+        for fr in frames:
+            o = oracle.conceal(p, fr.image, fr.lost)
+            q = np.where(fr.lost.astype(bool), np.clip(np.rint(o.image), 0, 255), fr.image)
+            psnrs.append(psnr_lost(q.astype(np.uint8), fr.image, fr.lost))
+            waves.append(int(o.waves))
+        res[name] = {"psnr_db": psnrs, "mean_psnr_db": float(np.mean(psnrs)), "waves": waves}
+    res["gain_db"] = res["optimized"]["mean_psnr_db"] - res["line_scan"]["mean_psnr_db"]
+    return res
+
+
+def end_to_end(fse, frames, precision, steps=2):
+    """The 64-frame batch from and to host memory (PCIe copies included)."""
+    p = fse.Params(border_d=BORDER, iterations=K_ITER, precision=precision)
+    imgs = [f.image for f in frames]
+    losts = [f.lost for f in frames]
+    with fse.Plan(p) as plan:
+        plan.fse_conceal_image(imgs, losts)
+        blocks = 0
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            res = plan.fse_conceal_image(imgs, losts)
+            blocks += sum(r.lost_blocks for r in res)
+        dt = time.perf_counter() - t0
+    return {"value": blocks / dt, "unit": "lost blocks/s", "ms_per_step": dt / steps * 1e3,
+            "form": "host uint8 frames in, host uint8 frames out, one call per step"}
+
+
 def serving_run(fse, synth, duration_s=3.0, warmup_s=0.5, rate_hz=240.0, seed=0):
     """Poisson stream of drifting-texture frames (30 % 1280x720, 50 % 1920x1080,
     20 % 3840x2160, 2-15 % slice losses) submitted in real time; frames are
@@ -169,6 +240,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-order", action="store_true")
+    ap.add_argument("--no-e2e", action="store_true")
     ap.add_argument("--precision", choices=("fp32", "fp32_rerank"), default="fp32_rerank",
                     help="arithmetic of the headline batched run")
     ap.add_argument("--seed", type=int, default=0)
@@ -288,10 +361,32 @@ def main():
         log(f"[bench] serving: p50 {serving['p50_frame_latency_ms']:.1f} ms, "
             f"p99 {serving['p99_frame_latency_ms']:.1f} ms over {serving['frames']} frames")
 
+    e2e = None
+    if not args.no_e2e:
+        log("[bench] end to end from host memory")
+        e2e = end_to_end(fse, frames, head_prec)
+        log(f"[bench] end to end: {e2e['value']:.0f} blocks/s")
+
+    order = None
+    if not args.no_order:
+        log("[bench] order comparison (512x512, p = 0.25)")
+        oframes = order_frames(synth)
+        order = {"gpu": order_comparison_gpu(fse, oframes, head_prec), "oracle": None}
+        log(f"[bench] order comparison: gain {order['gpu']['gain_db']:.3f} dB (GPU)")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
         cpu = cpu_baseline(frames)
+        if order is not None:
+            # the oracle's line scan is sequential: one 256x256 frame, with the
+            # GPU result on the same frame beside it
+            small = [synth.config2(seed=0, size=256)]
+            order["oracle"] = {"frames": "one 256x256 frame (seed 0), p = 0.25",
+                               "oracle": order_comparison_oracle(small),
+                               "gpu": order_comparison_gpu(fse, small, head_prec, reps=1)}
+            log(f"[bench] order comparison: gain {order['oracle']['oracle']['gain_db']:.3f} dB "
+                f"(oracle), {order['oracle']['gpu']['gain_db']:.3f} dB (GPU), 256x256")
 
     line = {
         "metric": "lost blocks extrapolated/s (K=200) + p99 frame latency, FP32 batched vs FP64 plain",
@@ -327,6 +422,8 @@ def main():
         "precision_sweep": sweep,
         "p99_frame_latency_ms": serving["p99_frame_latency_ms"] if serving else None,
         "serving": serving,
+        "end_to_end": e2e,
+        "order_comparison": order,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
