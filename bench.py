@@ -286,13 +286,14 @@ def main():
         for _ in range(warmup):
             plan.conceal_device(descs)
         torch.cuda.synchronize()
-        kms, tms, launches, blocks = 0.0, 0.0, 0, 0
+        kms, tms, busy, launches, blocks = 0.0, 0.0, 0.0, 0, 0
         t0 = time.perf_counter()
         for _ in range(steps):
             plan.conceal_device(descs)
             cs = plan.last_call_stats()
             kms += cs["kernel_ms"]
             tms += cs["transform_ms"]
+            busy += cs["busy_ms"]
             launches += cs["launches"]
             blocks += cs["blocks"]
         torch.cuda.synchronize()
@@ -300,6 +301,7 @@ def main():
         plan.close()
         return {"value": blocks / dt, "ms_per_step": dt / steps * 1e3,
                 "kernel_ms_per_step": kms / steps, "transform_ms_per_step": tms / steps,
+                "kernel_busy_ms_per_step": busy / steps, "groups": cs["groups"],
                 "launches_per_step": launches // steps,
                 "blocks_per_step": blocks // steps, "avg_launch_ms": kms / max(1, launches),
                 "blocks_per_launch": blocks / max(1, launches)}
@@ -328,7 +330,10 @@ def main():
     # mode the transforms run in a separate FP64 pass
     kflops = (ITER_FLOPS + SYNTH_FLOPS if args.precision == "fp32_rerank"
               else FLOPS_PER_BLOCK)
-    achieved = kflops * blocks_per_launch / (avg_launch_ms * 1e-3) / 1e12
+    # launches of different frame groups overlap: the kernel's flops over the
+    # time at least one of its launches ran (union of the launch intervals)
+    busy_ms = head["kernel_busy_ms_per_step"]
+    achieved = kflops * lost_blocks / (busy_ms * 1e-3) / 1e12
     traffic = measured_traffic(args.precision)
 
     fp64 = None
@@ -413,7 +418,11 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
                      "kernel": "fse_block_kernel<float>",
                      "avg_launch_ms": avg_launch_ms, "blocks_per_launch": blocks_per_launch,
+                     "kernel_busy_ms_per_step": busy_ms, "groups": head["groups"],
                      "flops_per_block": kflops,
+                     "achieved_note": "flops of all blocks of a step over the union of the "
+                                      "kernel's launch intervals (HIP events), since launches "
+                                      "of different frame groups overlap",
                      "traffic_note": "HBM bytes per launch from rocprofv3 FETCH_SIZE x2.0 + "
                                      "WRITE_SIZE x1.0 (copy-calibrated), taken on this kernel "
                                      "source; null when the source changed since",

@@ -188,17 +188,29 @@ int32_t fse_poll(fse_plan_t plan, uint64_t ticket, int32_t timeout_us);
 int32_t fse_schedule(int32_t hb, int32_t wb, const uint8_t *lost, int32_t order,
                      int32_t *wave_of, int32_t *seq);
 
-/* Device time of the per-block iteration kernel of the last
- * fse_conceal_image call, summed over its launches (one per step) and
- * measured with HIP events on the plan's stream, the number of those launches
- * and of the blocks they processed, the device time of the FP64 transform
- * pass (FSE_FP32_RERANK only) and the host wall time of the call. */
+/* Statistics of the last fse_conceal_image call.  The frames of a call run
+ * in `groups` groups, each as its own sequence of launches (one per step) on
+ * a stream of its own, so launches of different groups overlap in time.
+ *   kernel_ms    device time of the per-block iteration kernel, summed over
+ *                its launches (HIP events around every launch);
+ *   launches     number of those launches;  blocks: blocks they processed;
+ *   total_ms     host wall time of the call;
+ *   transform_ms device time of the FP64 transform pass, summed over its
+ *                launches (FSE_FP32_RERANK only);
+ *   span_ms      device time from the first to the end of the last
+ *                extrapolation launch (all groups);
+ *   groups       number of frame groups;
+ *   busy_ms      device time during which at least one launch of the
+ *                iteration kernel ran (union of the launch intervals). */
 typedef struct {
   double kernel_ms;
   int64_t launches;
   int64_t blocks;
   double total_ms;
   double transform_ms;
+  double span_ms;
+  int64_t groups;
+  double busy_ms;
 } fse_call_stats;
 int32_t fse_last_call_stats(fse_plan_t plan, fse_call_stats *out);
 

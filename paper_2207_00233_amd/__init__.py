@@ -94,7 +94,8 @@ class _Frame(ctypes.Structure):
 class _CallStats(ctypes.Structure):
     _fields_ = [("kernel_ms", ctypes.c_double), ("launches", ctypes.c_int64),
                 ("blocks", ctypes.c_int64), ("total_ms", ctypes.c_double),
-                ("transform_ms", ctypes.c_double)]
+                ("transform_ms", ctypes.c_double), ("span_ms", ctypes.c_double),
+                ("groups", ctypes.c_int64), ("busy_ms", ctypes.c_double)]
 
 
 @dataclasses.dataclass
@@ -307,7 +308,8 @@ class Plan:
         cs = _CallStats()
         _check(self._lib.fse_last_call_stats(self.handle, ctypes.byref(cs)), "fse_last_call_stats")
         return {"kernel_ms": cs.kernel_ms, "launches": cs.launches, "blocks": cs.blocks,
-                "total_ms": cs.total_ms, "transform_ms": cs.transform_ms}
+                "total_ms": cs.total_ms, "transform_ms": cs.transform_ms,
+                "span_ms": cs.span_ms, "groups": cs.groups, "busy_ms": cs.busy_ms}
 
     # -- fse_submit / fse_poll ------------------------------------------------
     def fse_submit(self, image: np.ndarray, lost: np.ndarray, want_float: bool = False,

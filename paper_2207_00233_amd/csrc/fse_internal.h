@@ -55,6 +55,16 @@ struct fse_plan_s {
     return n_items <= wide_threshold ? 16 : (n_items <= mid_threshold ? 8 : 4);
   }
   bool stagger = true;       // staggered frame starts inside a batch
+  // frames of a batch run in up to `groups` groups on streams of their own
+  // (0: by precision, measured on MI355X with the 64-frame batch: 3 groups
+  // for the re-rank mode, whose two kernels per step overlap best, else 2;
+  // more groups than hardware queues serialize)
+  int groups = 0;
+  int group_count() const {
+    return groups > 0 ? groups : (p.precision == FSE_FP32_RERANK ? 3 : 2);
+  }
+  std::vector<hipStream_t> gstreams;
+  std::vector<hipEvent_t> gjoin;
   // launch cost model used to stagger frames: max(latency, blocks / rate),
   // [0] = FP64, [1] = FP32; measured on MI355X for 16x16 blocks, d = 14, K = 200
   double model_latency_us[2] = {260.0, 150.0};

@@ -171,6 +171,20 @@ int plan_device_init(fse_plan_s* pl) {
 
 // ------------------------------------------------------------ batch execution
 
+// Group 0 runs on the plan's stream; groups 1.. on non-blocking streams of
+// their own (default priority), each with a join event, created on first use.
+static int ensure_group_streams(fse_plan_s* pl, int G) {
+  while ((int)pl->gstreams.size() < G - 1) {
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return FSE_ERR_DEVICE;
+    pl->gstreams.push_back(st);
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return FSE_ERR_DEVICE;
+    pl->gjoin.push_back(e);
+  }
+  return FSE_OK;
+}
+
 template <typename T>
 static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
   const fse_params& p = pl->p;
@@ -264,9 +278,8 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
   std::vector<const uint8_t*> flags(n);
   for (int f = 0; f < n; ++f) flags[f] = allflags.data() + io[f].flag_off;
 
-  // processing order per frame, merged by wave index
+  // processing order per frame
   std::vector<std::vector<int32_t>> wave_of(n), seq(n);
-  int max_waves = 0;
   // frames are scheduled independently, on up to 16 host threads
   std::vector<int> nwaves(n, 0);
   {
@@ -289,7 +302,6 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
   }
   for (int f = 0; f < n; ++f) {
     const int nw = nwaves[f];
-    max_waves = std::max(max_waves, nw);
     if (frames[f].stats) {
       fse_stats* st = frames[f].stats;
       st->waves = nw;
@@ -305,40 +317,72 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
       st->latency_ms = 0.0;
     }
   }
-  // frames start at staggered steps; step s holds wave s - off[f] of frame f
-  std::vector<int> off(n, 0);
-  if (n > 1 && pl->stagger) {
-    std::vector<std::vector<int>> sizes(n);
-    for (int f = 0; f < n; ++f) {
-      int nw = 0;
-      for (int32_t b : seq[f]) nw = std::max(nw, wave_of[f][b] + 1);
-      sizes[f].assign(nw, 0);
-      for (int32_t b : seq[f]) ++sizes[f][wave_of[f][b]];
+  // Frames are split into up to `groups` groups (largest first onto the
+  // group with the fewest lost blocks); each group runs its own sequence of
+  // steps on its own stream, so one group's small launches overlap another's.
+  // Inside a group frames start at staggered steps: step s of the group holds
+  // wave s - off[f] of its frame f.
+  const bool staged_mode = p.border_d > std::min(Bh, Bw);
+  const int G = staged_mode ? 1 : std::max(1, std::min(pl->group_count(), n));
+  std::vector<std::vector<int>> gframes(G);
+  {
+    std::vector<int> byload(n);
+    for (int f = 0; f < n; ++f) byload[f] = f;
+    std::stable_sort(byload.begin(), byload.end(),
+                     [&](int x, int y) { return seq[x].size() > seq[y].size(); });
+    std::vector<int64_t> load(G, 0);
+    for (int f : byload) {
+      const int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      gframes[g].push_back(f);
+      load[g] += (int64_t)seq[f].size();
     }
-    const bool fp64 = p.precision == FSE_FP64;
-    off = stagger_frames(sizes, fp64 ? pl->model_latency_us[0] : pl->model_latency_us[1],
-                         fp64 ? pl->model_rate[0] : pl->model_rate[1]);
+    for (auto& v : gframes) std::sort(v.begin(), v.end());
   }
+  const bool fp64 = p.precision == FSE_FP64;
   std::vector<int32_t> items;
-  std::vector<int64_t> wave_start(max_waves + 1, 0);
-  std::vector<size_t> pos(n, 0);
   std::vector<std::pair<int, int32_t>> item_src;  // (frame, block) per item
-  for (int step = 0; step < max_waves; ++step) {
-    wave_start[step] = (int64_t)items.size() / 2;
-    for (int f = 0; f < n; ++f) {
-      const int t = step - off[f];
-      while (t >= 0 && pos[f] < seq[f].size() && wave_of[f][seq[f][pos[f]]] == t) {
-        const int32_t b = seq[f][pos[f]++];
-        items.push_back(f);
-        items.push_back(((b / wb[f]) << 16) | (b % wb[f]));
-        item_src.emplace_back(f, b);
+  // gstart[g][t] = first item of step t of group g (items of all groups in
+  // one array, group after group)
+  std::vector<std::vector<int64_t>> gstart(G);
+  int max_steps = 0;
+  for (int g = 0; g < G; ++g) {
+    const std::vector<int>& fs = gframes[g];
+    const int m = (int)fs.size();
+    std::vector<int> off(m, 0);
+    int steps = 0;
+    for (int f : fs) steps = std::max(steps, nwaves[f]);
+    if (m > 1 && pl->stagger) {
+      std::vector<std::vector<int>> sizes(m);
+      for (int k = 0; k < m; ++k) {
+        const int f = fs[k];
+        sizes[k].assign(nwaves[f], 0);
+        for (int32_t b : seq[f]) ++sizes[k][wave_of[f][b]];
+      }
+      off = stagger_frames(sizes, fp64 ? pl->model_latency_us[0] : pl->model_latency_us[1],
+                           fp64 ? pl->model_rate[0] : pl->model_rate[1]);
+      for (int k = 0; k < m; ++k) steps = std::max(steps, off[k] + nwaves[fs[k]]);
+    }
+    gstart[g].assign(steps + 1, 0);
+    std::vector<size_t> pos(m, 0);
+    for (int step = 0; step < steps; ++step) {
+      gstart[g][step] = (int64_t)items.size() / 2;
+      for (int k = 0; k < m; ++k) {
+        const int f = fs[k];
+        const int t = step - off[k];
+        while (t >= 0 && pos[k] < seq[f].size() && wave_of[f][seq[f][pos[k]]] == t) {
+          const int32_t b = seq[f][pos[k]++];
+          items.push_back(f);
+          items.push_back(((b / wb[f]) << 16) | (b % wb[f]));
+          item_src.emplace_back(f, b);
+        }
       }
     }
+    gstart[g][steps] = (int64_t)items.size() / 2;
+    max_steps = std::max(max_steps, steps);
   }
-  wave_start[max_waves] = (int64_t)items.size() / 2;
-  const int64_t n_items = wave_start[max_waves];
+  const int64_t n_items = (int64_t)items.size() / 2;
 
-  const bool staged = p.border_d > std::min(Bh, Bw);
+  const bool staged = staged_mode;
   bool want_trace = false;
   for (int f = 0; f < n; ++f) want_trace |= frames[f].trace != nullptr;
   if ((rc = pl->items_dev.reserve(std::max<int64_t>(1, n_items) * 2 * sizeof(int32_t))))
@@ -379,39 +423,72 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
   a.empty_fill = p.empty_fill;
   a.rerank_gap = p.rerank_gap > 0.0 ? p.rerank_gap : 1e-4;
   const bool rerank = p.precision == FSE_FP32_RERANK;
+  // FP64 spectra: one slot per item of a step, per group (groups run at once)
+  std::vector<int64_t> spec_base(G + 1, 0);
+  for (int g = 0; g < G; ++g) {
+    int64_t mx = 0;
+    for (size_t t = 0; t + 1 < gstart[g].size(); ++t) mx = std::max(mx, gstart[g][t + 1] - gstart[g][t]);
+    spec_base[g + 1] = spec_base[g] + mx;
+  }
   a.spec64 = nullptr;
   if (rerank) {
-    int64_t max_step = 0;
-    for (int t = 0; t < max_waves; ++t) max_step = std::max(max_step, wave_start[t + 1] - wave_start[t]);
-    if ((rc = pl->spec64.reserve(std::max<int64_t>(1, max_step) * kSpecStride * sizeof(double))))
+    if ((rc = pl->spec64.reserve(std::max<int64_t>(1, spec_base[G]) * kSpecStride * sizeof(double))))
       return rc;
-    a.spec64 = (double*)pl->spec64.ptr;
   }
 
-  while ((int)pl->events.size() < 3 * max_waves) {
+  // streams: group 0 on the plan's stream, the other groups on streams forked
+  // from and joined back into it
+  if ((rc = ensure_group_streams(pl, G))) return rc;
+  int n_launch = 0;
+  for (int g = 0; g < G; ++g)
+    for (size_t t = 0; t + 1 < gstart[g].size(); ++t) n_launch += gstart[g][t + 1] > gstart[g][t];
+  while ((int)pl->events.size() < 3 * n_launch + 2) {
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return FSE_ERR_DEVICE;
     pl->events.push_back(e);
   }
-  for (int t = 0; t < max_waves; ++t) {
-    const int64_t i0 = wave_start[t], cnt = wave_start[t + 1] - i0;
-    a.items = (const int32_t*)pl->items_dev.ptr + 2 * i0;
-    a.staging = staged ? (T*)pl->staging.ptr : nullptr;
-    a.trace_u = want_trace ? (int32_t*)pl->trace_u.ptr + i0 * K : nullptr;
-    a.trace_dc = want_trace ? (T*)pl->trace_dc.ptr + i0 * K * 2 : nullptr;
-    const int waves = pl->waves_for(cnt);
-    if ((rc = chk(hipEventRecord(pl->events[3 * t], s)))) return rc;
-    if constexpr (std::is_same<T, float>::value) {
-      if (rerank && (rc = chk(launch_dft64(a, (const double*)pl->tbl_radial64.ptr, (int)cnt, s))))
+  hipEvent_t ev_fork = pl->events[3 * n_launch], ev_end = pl->events[3 * n_launch + 1];
+  if ((rc = chk(hipEventRecord(ev_fork, s)))) return rc;
+  for (int g = 1; g < G; ++g)
+    if ((rc = chk(hipStreamWaitEvent(pl->gstreams[g - 1], ev_fork, 0)))) return rc;
+  int li = 0;
+  for (int t = 0; t < max_steps; ++t) {
+    // blocks of this step over all groups, for the workgroup shape
+    int64_t step_total = 0;
+    for (int g = 0; g < G; ++g)
+      if (t + 1 < (int)gstart[g].size()) step_total += gstart[g][t + 1] - gstart[g][t];
+    for (int g = 0; g < G; ++g) {
+      if (t + 1 >= (int)gstart[g].size()) continue;
+      const int64_t i0 = gstart[g][t], cnt = gstart[g][t + 1] - i0;
+      if (cnt == 0) continue;
+      hipStream_t gs = g > 0 ? pl->gstreams[g - 1] : s;
+      a.items = (const int32_t*)pl->items_dev.ptr + 2 * i0;
+      a.staging = staged ? (T*)pl->staging.ptr : nullptr;
+      a.trace_u = want_trace ? (int32_t*)pl->trace_u.ptr + i0 * K : nullptr;
+      a.trace_dc = want_trace ? (T*)pl->trace_dc.ptr + i0 * K * 2 : nullptr;
+      if (rerank) a.spec64 = (double*)pl->spec64.ptr + spec_base[g] * kSpecStride;
+      const int waves = pl->waves_for(step_total);
+      if ((rc = chk(hipEventRecord(pl->events[3 * li], gs)))) return rc;
+      if constexpr (std::is_same<T, float>::value) {
+        if (rerank &&
+            (rc = chk(launch_dft64(a, (const double*)pl->tbl_radial64.ptr, (int)cnt, gs))))
+          return rc;
+      }
+      if ((rc = chk(hipEventRecord(pl->events[3 * li + 1], gs)))) return rc;
+      if ((rc = chk(launch_block<T>(a, (int)cnt, waves, gs, rerank ? 1 : 0)))) return rc;
+      if ((rc = chk(hipEventRecord(pl->events[3 * li + 2], gs)))) return rc;
+      if (staged && (rc = chk(launch_scatter<T>(work, state, a.frames, a.items, (int)cnt,
+                                                (const T*)pl->staging.ptr, Bh, Bw, gox, goy, gs))))
         return rc;
+      ++li;
     }
-    if ((rc = chk(hipEventRecord(pl->events[3 * t + 1], s)))) return rc;
-    if ((rc = chk(launch_block<T>(a, (int)cnt, waves, s, rerank ? 1 : 0)))) return rc;
-    if ((rc = chk(hipEventRecord(pl->events[3 * t + 2], s)))) return rc;
-    if (staged && (rc = chk(launch_scatter<T>(work, state, a.frames, a.items, (int)cnt,
-                                              (const T*)pl->staging.ptr, Bh, Bw, gox, goy, s))))
+  }
+  for (int g = 1; g < G; ++g) {
+    if ((rc = chk(hipEventRecord(pl->gjoin[g - 1], pl->gstreams[g - 1]))) ||
+        (rc = chk(hipStreamWaitEvent(s, pl->gjoin[g - 1], 0))))
       return rc;
   }
+  if ((rc = chk(hipEventRecord(ev_end, s)))) return rc;
 
   // outputs
   if ((rc = chk(launch_finalize<T>((const IoDesc*)pl->io_dev.ptr, n, max_pixels, state, work, s))))
@@ -434,15 +511,45 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
   if ((rc = chk(hipStreamSynchronize(s)))) return rc;
 
   double kms = 0.0, tms = 0.0;
-  for (int t = 0; t < max_waves; ++t) {
+  for (int t = 0; t < n_launch; ++t) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, pl->events[3 * t + 1], pl->events[3 * t + 2]) == hipSuccess) kms += ms;
     if (rerank && hipEventElapsedTime(&ms, pl->events[3 * t], pl->events[3 * t + 1]) == hipSuccess)
       tms += ms;
   }
+  float span = 0.f;
+  (void)hipEventElapsedTime(&span, ev_fork, ev_end);
+  // union of the iteration kernel's launch intervals (launches of different
+  // groups overlap)
+  double busy = 0.0;
+  {
+    std::vector<std::pair<float, float>> iv;
+    iv.reserve(n_launch);
+    for (int t = 0; t < n_launch; ++t) {
+      float a0 = 0.f, a1 = 0.f;
+      if (hipEventElapsedTime(&a0, ev_fork, pl->events[3 * t + 1]) == hipSuccess &&
+          hipEventElapsedTime(&a1, ev_fork, pl->events[3 * t + 2]) == hipSuccess)
+        iv.emplace_back(a0, a1);
+    }
+    std::sort(iv.begin(), iv.end());
+    float lo = 0.f, hi = -1.f;
+    for (const auto& x : iv) {
+      if (x.first > hi) {
+        if (hi > lo) busy += hi - lo;
+        lo = x.first;
+        hi = x.second;
+      } else {
+        hi = std::max(hi, x.second);
+      }
+    }
+    if (hi > lo) busy += hi - lo;
+  }
   pl->last.kernel_ms = kms;
   pl->last.transform_ms = tms;
-  pl->last.launches = max_waves;
+  pl->last.span_ms = span;
+  pl->last.busy_ms = busy;
+  pl->last.groups = G;
+  pl->last.launches = n_launch;
   pl->last.blocks = n_items;
 
   if (want_trace && n_items > 0) {
@@ -521,6 +628,10 @@ int32_t fse_plan(const fse_params* p, void* hip_stream, fse_plan_t* out) {
     }
     pl->own_stream = true;
   }
+  if (const char* env = std::getenv("FSE_FRAME_GROUPS")) {
+    const int g = std::atoi(env);
+    if (g >= 1 && g <= 16) pl->groups = g;
+  }
   if (const char* env = std::getenv("FSE_WAVE_THRESHOLDS")) {
     int t16 = 0, t8 = 0;
     if (std::sscanf(env, "%d,%d", &t16, &t8) == 2 && t16 >= 0 && t8 >= 0) {
@@ -549,6 +660,13 @@ int32_t fse_plan_destroy(fse_plan_t pl) {
   if (pl->stream) (void)hipStreamSynchronize(pl->stream);
   for (hipEvent_t e : pl->events) (void)hipEventDestroy(e);
   pl->events.clear();
+  for (hipStream_t st : pl->gstreams) {
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+  }
+  pl->gstreams.clear();
+  for (hipEvent_t e : pl->gjoin) (void)hipEventDestroy(e);
+  pl->gjoin.clear();
   DevBuf* bufs[] = {&pl->tbl_radial, &pl->tbl_twid, &pl->tbl_twid64, &pl->tbl_radial64,
                     &pl->spec64, &pl->work, &pl->state,
                     &pl->frames_dev, &pl->items_dev, &pl->u8_img, &pl->u8_lost, &pl->u8_out,

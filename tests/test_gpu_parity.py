@@ -367,6 +367,33 @@ def test_every_launch_shape_matches_oracle(monkeypatch, shape, precision):
         assert np.mean(errs <= FP32_TOL) >= 0.9
 
 
+# ------------------------------------------------------------ frame groups
+
+@pytest.mark.parametrize("precision", [fse.FSE_FP64, fse.FSE_FP32_RERANK, fse.FSE_FP32])
+def test_frame_groups_equal_one_group(monkeypatch, precision):
+    """A batch split into frame groups on separate streams gives bit for bit
+    the results of one group (each frame keeps its wave order; the workgroup
+    shape is pinned so that both runs use the same kernels)."""
+    monkeypatch.setenv("FSE_WAVE_THRESHOLDS", "0,0")
+    rng = np.random.default_rng(41)
+    frames = []
+    for (H, W) in [(96, 128), (64, 80), (130, 70), (48, 48), (112, 96), (80, 160)]:
+        img = synth.polygon_image(rng, H, W, radius=(8, 40))
+        frames.append((img, synth.slice_loss(rng, H, W, 16, (0.2, 0.5))))
+    imgs, losts = [f[0] for f in frames], [f[1] for f in frames]
+    p = fse.Params(border_d=14, iterations=60, precision=precision)
+    res = {}
+    for groups in ("1", "4"):
+        monkeypatch.setenv("FSE_FRAME_GROUPS", groups)
+        with fse.Plan(p) as plan:
+            res[groups] = plan.fse_conceal_image(imgs, losts, want_float=True, trace=True)
+            assert plan.last_call_stats()["groups"] == int(groups)
+    for a, b in zip(res["1"], res["4"]):
+        np.testing.assert_array_equal(a.out_f, b.out_f)
+        np.testing.assert_array_equal(a.out, b.out)
+        np.testing.assert_array_equal(a.trace_u, b.trace_u)
+
+
 # ------------------------------------------------------------ single launch
 
 @pytest.mark.skip(reason="the single-launch batch path (one dependency-driven launch with "
