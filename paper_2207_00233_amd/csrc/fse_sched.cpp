@@ -33,58 +33,76 @@ int schedule_blocks(int hb, int wb, const uint8_t* lost, int order, int32_t* wav
       }
     return w;
   }
-  // Neighbour lists (8-neighbourhood, inside the grid).
-  auto for_neighbours = [&](int b, auto&& fn) {
-    const int i = b / wb, j = b % wb;
-    const int i0 = i > 0 ? i - 1 : 0, i1 = i + 1 < hb ? i + 1 : hb - 1;
-    const int j0 = j > 0 ? j - 1 : 0, j1 = j + 1 < wb ? j + 1 : wb - 1;
-    for (int y = i0; y <= i1; ++y)
-      for (int x = j0; x <= j1; ++x)
-        if (y != i || x != j) fn(y * wb + x);
+  // The grid padded by one ring of cells outside the image: a neighbour
+  // outside counts as not extrapolated, which is the +3 margin / +5 corner
+  // rule, and the 8 neighbours of a cell are at fixed offsets.
+  const int W2 = wb + 2, H2 = hb + 2, n2 = W2 * H2;
+  const int nbr[8] = {-W2 - 1, -W2, -W2 + 1, -1, 1, W2 - 1, W2, W2 + 1};
+  std::vector<uint8_t> open(n2, 1);  // 1: not extrapolated (outside, or lost)
+  for (int i = 0; i < hb; ++i)
+    for (int j = 0; j < wb; ++j) open[(i + 1) * W2 + j + 1] = lost[i * wb + j] ? 1 : 0;
+  // N per cell (-1: finished or outside); pending cells by N (0..8) in one
+  // bitset per N over the padded index, so a wave visits only the cells with
+  // the smallest N, in raster order
+  std::vector<int8_t> cnt(n2, -1);
+  const int nwords = (n2 + 63) / 64;
+  std::vector<uint64_t> bucket((size_t)9 * nwords, 0);
+  auto set_bit = [&](int c, int p) { bucket[(size_t)c * nwords + (p >> 6)] |= 1ull << (p & 63); };
+  auto clr_bit = [&](int c, int p) {
+    bucket[(size_t)c * nwords + (p >> 6)] &= ~(1ull << (p & 63));
   };
-  std::vector<int> cnt(nb, 0);
-  std::vector<int32_t> pending;
-  pending.reserve(nb);
-  for (int b = 0; b < nb; ++b) {
-    int inside = 0;
-    for_neighbours(b, [&](int q) {
-      ++inside;
-      if (lost[q]) ++cnt[b];
-    });
-    cnt[b] += 8 - inside;
-    if (lost[b]) pending.push_back(b);
-    else cnt[b] = -1;
-  }
-  // `pending` stays in raster order; finished blocks are compacted out.
-  std::vector<uint8_t> blocked(nb, 0);
+  int npending = 0;
+  for (int i = 1; i <= hb; ++i)
+    for (int j = 1; j <= wb; ++j) {
+      const int p = i * W2 + j;
+      if (!lost[(i - 1) * wb + j - 1]) continue;
+      int c = 0;
+      for (int k = 0; k < 8; ++k) c += open[p + nbr[k]];
+      cnt[p] = (int8_t)c;
+      set_bit(c, p);
+      ++npending;
+    }
+  std::vector<uint8_t> blocked(n2, 0);
   std::vector<int32_t> taken;
   int wave = 0;
-  while (!pending.empty()) {
-    int nmin = cnt[pending[0]];
-    for (int32_t b : pending)
-      if (cnt[b] < nmin) nmin = cnt[b];
-    taken.clear();
-    for (int32_t b : pending) {
-      if (cnt[b] != nmin || blocked[b]) continue;
-      taken.push_back(b);
-      // a block adjacent to a taken one cannot join this wave
-      for_neighbours(b, [&](int q) { blocked[q] = 1; });
+  while (npending > 0) {
+    int nmin = 0;
+    for (;; ++nmin) {
+      const uint64_t* w = &bucket[(size_t)nmin * nwords];
+      bool any = false;
+      for (int k = 0; k < nwords && !any; ++k) any = w[k] != 0;
+      if (any) break;
     }
-    for (int32_t b : taken) {
+    taken.clear();
+    const uint64_t* w = &bucket[(size_t)nmin * nwords];
+    for (int k = 0; k < nwords; ++k) {
+      for (uint64_t x = w[k]; x; x &= x - 1) {
+        const int p = (k << 6) | __builtin_ctzll(x);
+        if (blocked[p]) continue;
+        taken.push_back(p);
+        // a block adjacent to a taken one cannot join this wave
+        for (int q = 0; q < 8; ++q) blocked[p + nbr[q]] = 1;
+      }
+    }
+    for (int32_t p : taken) {
+      const int b = (p / W2 - 1) * wb + (p % W2 - 1);
       wave_of[b] = wave;
       if (seq) seq->push_back(b);
-      for_neighbours(b, [&](int q) { blocked[q] = 0; });
+      for (int q = 0; q < 8; ++q) blocked[p + nbr[q]] = 0;
     }
-    for (int32_t b : taken) {
-      cnt[b] = -1;
-      for_neighbours(b, [&](int q) {
-        if (cnt[q] >= 0) --cnt[q];
-      });
+    for (int32_t p : taken) {
+      clr_bit(nmin, p);
+      cnt[p] = -1;
+      --npending;
+      for (int k = 0; k < 8; ++k) {
+        const int q = p + nbr[k];
+        if (cnt[q] >= 0) {
+          clr_bit(cnt[q], q);
+          --cnt[q];
+          set_bit(cnt[q], q);
+        }
+      }
     }
-    size_t k = 0;
-    for (int32_t b : pending)
-      if (cnt[b] >= 0) pending[k++] = b;
-    pending.resize(k);
     ++wave;
   }
   return wave;
