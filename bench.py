@@ -39,9 +39,9 @@ PEAK_FP32_PUBLISHED = 157.3
 
 
 def measured_traffic(precision):
-    """HBM bytes per launch of the block kernel from the committed rocprofv3
-    FETCH_SIZE/WRITE_SIZE measurement, if it was taken on this kernel source
-    and precision; None otherwise."""
+    """HBM bytes of the block kernel over one step (all its launches) from the
+    committed rocprofv3 FETCH_SIZE/WRITE_SIZE measurement, if it was taken on
+    this kernel source and precision; None otherwise."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "fse_block_kernel_traffic.json")
     try:
@@ -53,7 +53,7 @@ def measured_traffic(precision):
         h.update(open(os.path.join(ROOT, fn), "rb").read())
     if rec.get("precision") != precision or rec.get("kernel_source_sha256") != h.hexdigest():
         return None
-    return rec["traffic_bytes_per_launch"]
+    return rec["traffic_bytes_per_step"]
 
 
 def log(*a):
@@ -423,9 +423,10 @@ def main():
                      "achieved_note": "flops of all blocks of a step over the union of the "
                                       "kernel's launch intervals (HIP events), since launches "
                                       "of different frame groups overlap",
-                     "traffic_note": "HBM bytes per launch from rocprofv3 FETCH_SIZE x2.0 + "
-                                     "WRITE_SIZE x1.0 (copy-calibrated), taken on this kernel "
-                                     "source; null when the source changed since",
+                     "traffic_note": "HBM bytes of the kernel per step (all launches) from "
+                                     "rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0 (copy-"
+                                     "calibrated), taken on this kernel source; null when the "
+                                     "source changed since",
                      "frac_of_published_fp32_peak": achieved / PEAK_FP32_PUBLISHED},
         "fp64_plain": fp64,
         "precision_sweep": sweep,
