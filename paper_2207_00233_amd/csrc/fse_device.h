@@ -60,6 +60,7 @@ constexpr int64_t kSpecStride = 4 * kFft * kFft + 32;  // doubles per item (256-
 // Byte offsets of the dynamic LDS regions of the fused block kernel with
 // `waves` wavefronts per workgroup (rows = 64 / waves spectrum rows each).
 struct LdsLayout {
+  int64_t cs;        // compact staging (FP64 transform pass): weight classes
   int64_t bx, bw;    // phase B: row DFTs of x and w (M x 33 complex each)
   int64_t hist_dc;   // K complex coefficient increments
   int64_t hist_u;    // K selected indices
@@ -78,6 +79,7 @@ __host__ __device__ inline int64_t align16(int64_t v) { return (v + 15) & ~15LL;
 __host__ __device__ inline LdsLayout lds_layout(int M, int N, int K, int waves, int tsize,
                                                 bool stage_needed = true) {
   LdsLayout L;
+  L.cs = 0;
   const int NP = N | 1;  // odd row pitch of the staged area
   const int rows = kFft / waves;
   const int64_t stage_xw = 2LL * M * NP * tsize;
@@ -95,6 +97,29 @@ __host__ __device__ inline LdsLayout lds_layout(int M, int N, int K, int waves, 
   L.cand = L.slots + 2LL * waves * 32;
   L.misc = L.cand + 2LL * waves * 32;
   L.misc = align16(L.misc);
+  L.total = L.misc + 32;
+  return L;
+}
+
+// LDS of the FP64 transform pass of the re-rank mode: compact staging (float
+// samples, one byte per weight class, the row DFTs of x and w in double), then
+// the 64 x 64 complex double exchange buffer of the column DFT and unpack over
+// the same bytes, twiddles and slots; no iteration state.
+__host__ __device__ inline LdsLayout dft_layout(int M, int N, int waves) {
+  LdsLayout L;
+  const int NP = N | 1;
+  L.cs = align16((int64_t)M * NP * 4);
+  L.bx = align16(L.cs + (int64_t)M * NP);
+  L.bw = L.bx + (int64_t)M * kHalf * 2 * 8;
+  const int64_t stage = L.bw + (int64_t)M * kHalf * 2 * 8;
+  const int64_t zex = (int64_t)kFft * kFft * 2 * 8;
+  const int64_t region = align16(stage > zex ? stage : zex);
+  L.hist_dc = L.hist_u = region;  // unused
+  L.tw64 = region;
+  L.twt = L.tw64 + kFft * 2 * 8;
+  L.slots = align16(L.twt + kFft * 2 * 8);
+  L.cand = L.slots + 2LL * waves * 32;
+  L.misc = align16(L.cand);
   L.total = L.misc + 32;
   return L;
 }

@@ -45,6 +45,7 @@ struct fse_plan_s {
   fse::DevBuf spec64;          // FP64 spectra of a step (re-rank mode)
   fse::DevBuf work, state, frames_dev, items_dev, u8_img, u8_lost, u8_out, fout, staging,
       trace_u, trace_dc, flags_dev, io_dev;
+  fse::HostBuf pin_in, pin_out;  // pinned staging of host frames (inputs, 8-bit outputs)
   std::vector<hipEvent_t> events;
   // wavefronts per block by launch size: at most wide_threshold blocks -> 16,
   // at most mid_threshold -> 8, else 4 (fewer blocks than the GPU holds leave

@@ -137,7 +137,10 @@ struct Slot {
 // reads the working image in TI.  Returns W0 = sum of weights; when W0 > 0,
 // rr/ri hold X[k] and wvr/wvi hold W[k] for k1 = ROWS wave + j, k2 = lane.
 // Ends with a barrier, after which the LDS region may be reused.
-template <typename T, typename TI, int WAVES>
+// COMPACT: phase A stages the samples as TI and one weight class per sample
+// (the weights are formed again in phase B from the radial table), which
+// keeps the staging below the 64 x 64 complex exchange buffer.
+template <typename T, typename TI, int WAVES, bool COMPACT = false>
 __device__ __forceinline__ T forward_transforms(unsigned char* smem, const LdsLayout& L, int M,
                                                 int N, const T* radial, T delta, T zscale,
                                                 const TI* img, const uint8_t* st, int H, int W,
@@ -152,6 +155,8 @@ __device__ __forceinline__ T forward_transforms(unsigned char* smem, const LdsLa
   const int NP = N | 1;
   T* xs = reinterpret_cast<T*>(smem);
   T* ws = xs + M * NP;
+  TI* fs = reinterpret_cast<TI*>(smem);                   // COMPACT: samples
+  uint8_t* cs = reinterpret_cast<uint8_t*>(smem + L.cs);  // COMPACT: 0 none, 1 known, 2 recon
   T* bx = reinterpret_cast<T*>(smem + L.bx);
   T* bw = reinterpret_cast<T*>(smem + L.bw);
   T* Zl = reinterpret_cast<T*>(smem);  // 64 x 64 complex, after phase B
@@ -164,15 +169,24 @@ __device__ __forceinline__ T forward_transforms(unsigned char* smem, const LdsLa
     const int m = i / N, n = i - m * N;
     const int y = oy + m, x = ox + n;
     T wv = T(0), xv = T(0);
+    TI f = TI(0);
+    uint8_t c = 0;
     if (y >= 0 && y < H && x >= 0 && x < W) {
       const int64_t p = (int64_t)y * W + x;
       const uint8_t s = st[p];
       const T fac = s == kKnown ? T(1) : (s == kRecon ? delta : T(0));
+      c = s == kKnown ? 1 : (s == kRecon ? 2 : 0);
+      f = img[p];
       wv = radial[i] * fac;
-      xv = (T)img[p] * wv;
+      xv = (T)f * wv;
     }
-    ws[m * NP + n] = wv;
-    xs[m * NP + n] = xv;
+    if constexpr (COMPACT) {
+      fs[m * NP + n] = f;
+      cs[m * NP + n] = c;
+    } else {
+      ws[m * NP + n] = wv;
+      xs[m * NP + n] = xv;
+    }
     wsum += wv;
   }
   wsum = wave_sum(wsum);
@@ -190,7 +204,16 @@ __device__ __forceinline__ T forward_transforms(unsigned char* smem, const LdsLa
     for (int q = 0; q < QB; ++q) axr[q] = axi[q] = awr[q] = awi[q] = T(0);
     if (lane < M) {
       for (int n = 0; n < N; ++n) {
-        const T xv = xs[lane * NP + n], wv = ws[lane * NP + n];
+        T xv, wv;
+        if constexpr (COMPACT) {
+          const uint8_t c = cs[lane * NP + n];
+          const T r = radial[lane * N + n];
+          wv = c == 1 ? r : (c == 2 ? r * delta : T(0));
+          xv = (T)fs[lane * NP + n] * wv;
+        } else {
+          xv = xs[lane * NP + n];
+          wv = ws[lane * NP + n];
+        }
 #pragma unroll
         for (int q = 0; q < QB; ++q) {
           const int t = ((wave + WAVES * q) * n) & (kFft - 1);
@@ -333,7 +356,7 @@ __global__ __launch_bounds__(64 * WAVES) void fse_dft64_kernel(BlockArgs<float> 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = uniform_int(tid >> 6);
-  const LdsLayout L = lds_layout(a.M, a.N, a.K, WAVES, (int)sizeof(double));
+  const LdsLayout L = dft_layout(a.M, a.N, WAVES);
   const int item = blockIdx.x;
   const int fr = a.items[2 * item], bij = a.items[2 * item + 1];
   const int bi = bij >> 16, bj = bij & 0xffff;
@@ -342,7 +365,7 @@ __global__ __launch_bounds__(64 * WAVES) void fse_dft64_kernel(BlockArgs<float> 
   load_twiddles<double>(smem, L, a.twid64);
   VecR<double, ROWS> rr, ri;
   double wvr[ROWS], wvi[ROWS];
-  const double W0 = forward_transforms<double, float, WAVES>(
+  const double W0 = forward_transforms<double, float, WAVES, true>(
       smem, L, a.M, a.N, radial64, a.delta64, 128.0, a.work + fd.off, a.state + fd.off,
       fd.H, fd.W, by0 - a.d, bx0 - a.d, lane, wave, rr, ri, wvr, wvi);
   double* out = a.spec64 + (int64_t)item * kSpecStride;
@@ -843,7 +866,7 @@ hipError_t launch_dft64(const BlockArgs<float>& a, const double* radial64, int n
                         hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   static size_t attr_bytes = 0;
-  const size_t lds = (size_t)lds_bytes<double>(a.M, a.N, a.K, 4, true);
+  const size_t lds = (size_t)dft_layout(a.M, a.N, 4).total;
   return launch_with_lds(fse_dft64_kernel<4>, attr_bytes, n_items, 256, lds, s, a, radial64);
 }
 

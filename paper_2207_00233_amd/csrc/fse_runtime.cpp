@@ -171,6 +171,23 @@ int plan_device_init(fse_plan_s* pl) {
 
 // ------------------------------------------------------------ batch execution
 
+// fn(0..n-1) on up to 16 host threads.
+template <typename F>
+static void parallel_for(int n, F&& fn) {
+  const int nt = std::min<int>(n, std::min(16u, std::max(1u, std::thread::hardware_concurrency())));
+  if (nt <= 1) {
+    for (int i = 0; i < n; ++i) fn(i);
+    return;
+  }
+  std::atomic<int> next{0};
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nt; ++t)
+    pool.emplace_back([&] {
+      for (int i = next++; i < n; i = next++) fn(i);
+    });
+  for (auto& th : pool) th.join();
+}
+
 // Group 0 runs on the plan's stream; groups 1.. on non-blocking streams of
 // their own (default priority), each with a join event, created on first use.
 static int ensure_group_streams(fse_plan_s* pl, int G) {
@@ -232,7 +249,25 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
     return rc;
   if (!dev) {
     if ((rc = pl->u8_img.reserve(total)) || (rc = pl->u8_lost.reserve(total)) ||
-        (rc = pl->u8_out.reserve(total)) || (fout_bytes && (rc = pl->fout.reserve(fout_bytes))))
+        (rc = pl->u8_out.reserve(total)) || (fout_bytes && (rc = pl->fout.reserve(fout_bytes))) ||
+        (rc = pl->pin_in.reserve(2 * total)) || (rc = pl->pin_out.reserve(total)))
+      return rc;
+    // host frames: rows into pinned staging on host threads, then one DMA per
+    // arena (pageable 2-D copies would go row by row)
+    uint8_t* pimg = (uint8_t*)pl->pin_in.ptr;
+    uint8_t* plost = pimg + total;
+    parallel_for(n, [&](int f) {
+      const fse_frame& fr = frames[f];
+      const int H = fr.height, W = fr.width;
+      uint8_t* a = pimg + fd[f].off;
+      uint8_t* b = plost + fd[f].off;
+      for (int y = 0; y < H; ++y) {
+        std::memcpy(a + (int64_t)y * W, fr.image + (int64_t)y * fr.stride, W);
+        std::memcpy(b + (int64_t)y * W, fr.lost + (int64_t)y * fr.lost_stride, W);
+      }
+    });
+    if ((rc = chk(hipMemcpyAsync(pl->u8_img.ptr, pimg, total, hipMemcpyHostToDevice, s))) ||
+        (rc = chk(hipMemcpyAsync(pl->u8_lost.ptr, plost, total, hipMemcpyHostToDevice, s))))
       return rc;
   }
   T* work = (T*)pl->work.ptr;
@@ -252,9 +287,6 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
     } else {
       uint8_t* a = (uint8_t*)pl->u8_img.ptr + fd[f].off;
       uint8_t* b = (uint8_t*)pl->u8_lost.ptr + fd[f].off;
-      if ((rc = chk(hipMemcpy2DAsync(a, W, fr.image, fr.stride, W, H, hipMemcpyHostToDevice, s))) ||
-          (rc = chk(hipMemcpy2DAsync(b, W, fr.lost, fr.lost_stride, W, H, hipMemcpyHostToDevice, s))))
-        return rc;
       io[f].image = a;
       io[f].lost = b;
       io[f].out = (uint8_t*)pl->u8_out.ptr + fd[f].off;
@@ -494,12 +526,11 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
   if ((rc = chk(launch_finalize<T>((const IoDesc*)pl->io_dev.ptr, n, max_pixels, state, work, s))))
     return rc;
   if (!dev) {
+    if ((rc = chk(hipMemcpyAsync(pl->pin_out.ptr, pl->u8_out.ptr, total, hipMemcpyDeviceToHost, s))))
+      return rc;
     for (int f = 0; f < n; ++f) {
       const fse_frame& fr = frames[f];
       const int H = fr.height, W = fr.width;
-      if ((rc = chk(hipMemcpy2DAsync(fr.out, fr.out_stride, io[f].out, W, W, H,
-                                     hipMemcpyDeviceToHost, s))))
-        return rc;
       if (fr.out_f32 && (rc = chk(hipMemcpyAsync(fr.out_f32, io[f].of32, (size_t)H * W * 4,
                                                  hipMemcpyDeviceToHost, s))))
         return rc;
@@ -509,6 +540,15 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
     }
   }
   if ((rc = chk(hipStreamSynchronize(s)))) return rc;
+  if (!dev) {
+    const uint8_t* pout = (const uint8_t*)pl->pin_out.ptr;
+    parallel_for(n, [&](int f) {
+      const fse_frame& fr = frames[f];
+      for (int y = 0; y < fr.height; ++y)
+        std::memcpy(fr.out + (int64_t)y * fr.out_stride, pout + fd[f].off + (int64_t)y * fr.width,
+                    fr.width);
+    });
+  }
 
   double kms = 0.0, tms = 0.0;
   for (int t = 0; t < n_launch; ++t) {
@@ -673,6 +713,8 @@ int32_t fse_plan_destroy(fse_plan_t pl) {
                     &pl->fout, &pl->staging, &pl->trace_u, &pl->trace_dc, &pl->flags_dev,
                     &pl->io_dev};
   for (DevBuf* b : bufs) b->release();
+  pl->pin_in.release();
+  pl->pin_out.release();
   if (pl->own_stream && pl->stream) (void)hipStreamDestroy(pl->stream);
   delete pl;
   return FSE_OK;
