@@ -192,6 +192,32 @@ def isolated_block_loss(rng: np.random.Generator, height: int, width: int,
     return block_loss_mask(height, width, block, keep)
 
 
+def consecutive_loss(rng: np.random.Generator, height: int, width: int, size: int = 16,
+                     runs: int = 8, length=(3, 9)) -> np.ndarray:
+    """Consecutive losses of `size` samples width: horizontal and vertical runs
+    of `length` cells of size x size samples on the cell grid (the paper's
+    consecutive-loss pattern)."""
+    hb, wb = height // size, width // size
+    cells = np.zeros((hb, wb), bool)
+    for _ in range(runs):
+        n = int(rng.integers(length[0], length[1] + 1))
+        if rng.random() < 0.5:
+            i, j = int(rng.integers(0, hb)), int(rng.integers(0, max(1, wb - n + 1)))
+            cells[i, j:j + n] = True
+        else:
+            i, j = int(rng.integers(0, max(1, hb - n + 1))), int(rng.integers(0, wb))
+            cells[i:i + n, j] = True
+    return block_loss_mask(height, width, size, cells)
+
+
+def mixed_loss(rng: np.random.Generator, height: int, width: int, size: int = 16,
+               p_isolated: float = 0.12, runs: int = 6) -> np.ndarray:
+    """Isolated size x size losses together with consecutive runs (the
+    paper's mixed-loss pattern)."""
+    iso = isolated_block_loss(rng, height, width, size, p_isolated)
+    return np.maximum(iso, consecutive_loss(rng, height, width, size, runs))
+
+
 # --------------------------------------------------------------------------
 # The five workload recipes
 # --------------------------------------------------------------------------
