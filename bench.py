@@ -124,33 +124,41 @@ def order_comparison_gpu(fse, frames, precision, reps=3):
     return res
 
 
-def subblock_order_gpu(fse, synth, precision, size=512, seed=0, blocks=(16, 8, 4, 2)):
+def subblock_order_gpu(fse, synth, precision, size=512, seeds=(0, 1, 2, 3),
+                       blocks=(16, 8, 4, 2)):
     """The paper's order experiment: 16-sample isolated, consecutive and mixed
     losses, each processed with blocks of 16, 8, 4 or 2 samples (d = 16, so
     blocks smaller than the border read their wave's snapshot), optimized
-    order against line scan; PSNR on the lost samples (GPU)."""
-    rng = np.random.default_rng(seed)
-    img = synth.polygon_image(rng, size, size)
-    patterns = {"isolated": synth.isolated_block_loss(rng, size, size, 16, 0.25),
-                "consecutive": synth.consecutive_loss(rng, size, size),
-                "mixed": synth.mixed_loss(rng, size, size)}
+    order against line scan; PSNR on the lost samples per image and the mean
+    gain over the images (GPU)."""
     res = {}
-    for pname, lost in patterns.items():
-        rows = {}
-        for b in blocks:
-            r = {}
-            for oname, order in (("line_scan", fse.FSE_ORDER_LINESCAN),
-                                 ("optimized", fse.FSE_ORDER_OPTIMIZED)):
-                p = fse.Params(block_w=b, block_h=b, border_d=16, iterations=K_ITER,
-                               precision=precision, order=order)
-                with fse.Plan(p) as plan:
-                    t0 = time.perf_counter()
-                    out = plan.fse_conceal_image([img], [lost])[0]
-                    r[oname] = {"psnr_db": psnr_lost(out.out, img, lost), "waves": out.waves,
-                                "ms": (time.perf_counter() - t0) * 1e3}
-            r["gain_db"] = r["optimized"]["psnr_db"] - r["line_scan"]["psnr_db"]
-            rows[f"{b}x{b}"] = r
-        res[pname] = {"loss_fraction": float(lost.mean()), "blocks": rows}
+    for pname in ("isolated", "consecutive", "mixed"):
+        rows = {f"{b}x{b}": {"gain_db": [], "line_scan_db": [], "optimized_db": [],
+                             "waves": [], "line_scan_waves": []} for b in blocks}
+        for seed in seeds:
+            rng = np.random.default_rng(seed)
+            img = synth.polygon_image(rng, size, size)
+            lost = {"isolated": lambda: synth.isolated_block_loss(rng, size, size, 16, 0.25),
+                    "consecutive": lambda: synth.consecutive_loss(rng, size, size),
+                    "mixed": lambda: synth.mixed_loss(rng, size, size)}[pname]()
+            for b in blocks:
+                r = {}
+                for oname, order in (("line_scan", fse.FSE_ORDER_LINESCAN),
+                                     ("optimized", fse.FSE_ORDER_OPTIMIZED)):
+                    p = fse.Params(block_w=b, block_h=b, border_d=16, iterations=K_ITER,
+                                   precision=precision, order=order)
+                    with fse.Plan(p) as plan:
+                        out = plan.fse_conceal_image([img], [lost])[0]
+                    r[oname] = (psnr_lost(out.out, img, lost), out.waves)
+                row = rows[f"{b}x{b}"]
+                row["line_scan_db"].append(r["line_scan"][0])
+                row["optimized_db"].append(r["optimized"][0])
+                row["gain_db"].append(r["optimized"][0] - r["line_scan"][0])
+                row["waves"].append(r["optimized"][1])
+                row["line_scan_waves"].append(r["line_scan"][1])
+        for row in rows.values():
+            row["mean_gain_db"] = float(np.mean(row["gain_db"]))
+        res[pname] = rows
     return res
 
 
@@ -411,8 +419,8 @@ def main():
         log("[bench] order comparison with sub-blocks (isolated / consecutive / mixed)")
         order["subblocks"] = subblock_order_gpu(fse, synth, head_prec)
         for pn, v in order["subblocks"].items():
-            log(f"[bench]   {pn}: " + ", ".join(f"{b} {r['gain_db']:+.2f} dB"
-                                              for b, r in v["blocks"].items()))
+            log(f"[bench]   {pn}: " + ", ".join(f"{b} {r['mean_gain_db']:+.2f} dB"
+                                              for b, r in v.items()))
 
     cpu = None
     if not args.no_cpu_baseline:
