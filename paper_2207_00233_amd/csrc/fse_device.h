@@ -77,7 +77,7 @@ __host__ __device__ inline int64_t align16(int64_t v) { return (v + 15) & ~15LL;
 // `stage` = false for the re-rank iteration kernel, which receives its
 // spectra from the FP64 transform pass and needs no transform staging.
 __host__ __device__ inline LdsLayout lds_layout(int M, int N, int K, int waves, int tsize,
-                                                bool stage_needed = true) {
+                                                bool stage_needed = true, int wrap = -1) {
   LdsLayout L;
   L.cs = 0;
   const int NP = N | 1;  // odd row pitch of the staged area
@@ -86,8 +86,10 @@ __host__ __device__ inline LdsLayout lds_layout(int M, int N, int K, int waves, 
   L.bx = stage_xw;
   L.bw = L.bx + (int64_t)M * kHalf * 2 * tsize;
   const int64_t stage = stage_needed ? L.bw + (int64_t)M * kHalf * 2 * tsize : 0;
-  // the W spectrum with rows - 1 wrap-around rows (rows 64.. repeat 0..)
-  const int64_t wreg = (int64_t)(kFft + rows - 1) * kFft * 2 * tsize;
+  // the W spectrum with `wrap` (default rows - 1) wrap-around rows (rows
+  // 64.. repeat 0..), so that a window of a wavefront's rows never wraps
+  if (wrap < 0) wrap = rows - 1;
+  const int64_t wreg = (int64_t)(kFft + wrap) * kFft * 2 * tsize;
   const int64_t region = align16(stage > wreg ? stage : wreg);
   L.hist_dc = region;
   L.hist_u = L.hist_dc + (int64_t)K * 2 * tsize;
@@ -125,8 +127,9 @@ __host__ __device__ inline LdsLayout dft_layout(int M, int N, int waves) {
 }
 
 template <typename T>
-inline int64_t lds_bytes(int M, int N, int K, int waves, bool stage_needed = true) {
-  return lds_layout(M, N, K, waves, (int)sizeof(T), stage_needed).total;
+inline int64_t lds_bytes(int M, int N, int K, int waves, bool stage_needed = true,
+                         int wrap = -1) {
+  return lds_layout(M, N, K, waves, (int)sizeof(T), stage_needed, wrap).total;
 }
 
 }  // namespace fse

@@ -382,10 +382,43 @@ __global__ __launch_bounds__(64 * WAVES) void fse_dft64_kernel(BlockArgs<float> 
   }
 }
 
+// Spectrum rows of wavefront `wave`: ROWS consecutive rows, or with SPLIT two
+// windows of ROWS/2 rows (w ROWS/2 .. and 32 + w ROWS/2 ..), which needs only
+// ROWS/2 - 1 wrap-around rows of W in LDS.
+template <int WAVES, bool SPLIT>
+__device__ __forceinline__ int row_of(int wave, int j) {
+  constexpr int ROWS = kFft / WAVES;
+  if constexpr (SPLIT)
+    return (j < ROWS / 2 ? 0 : kFft / 2 - ROWS / 2) + (ROWS / 2) * wave + j;
+  else
+    return ROWS * wave + j;
+}
+
+// Inverse of row_of: the wavefront that owns spectrum row `row`, and the
+// index j of that row in its registers.
+template <int WAVES, bool SPLIT>
+__device__ __forceinline__ int wave_of_row(int row) {
+  constexpr int ROWS = kFft / WAVES;
+  if constexpr (SPLIT)
+    return (row & (kFft / 2 - 1)) / (ROWS / 2);
+  else
+    return row / ROWS;
+}
+
+template <int WAVES, bool SPLIT>
+__device__ __forceinline__ int j_of_row(int row, int wave) {
+  constexpr int ROWS = kFft / WAVES;
+  if constexpr (SPLIT)
+    return (row & (kFft / 2 - 1)) - (ROWS / 2) * wave + (row >= kFft / 2 ? ROWS / 2 : 0);
+  else
+    return row - ROWS * wave;
+}
+
 // RERANK (T = float only): spectra come from fse_dft64_kernel, and near-tied
 // selections are re-scored exactly in double.
 template <typename T, int WAVES, bool RERANK>
-__global__ __launch_bounds__(64 * WAVES) void fse_block_kernel(BlockArgs<T> a) {
+__global__ __launch_bounds__(64 * WAVES, (RERANK && WAVES == 4) ? 4 : 1) void fse_block_kernel(
+    BlockArgs<T> a) {
   constexpr int THREADS = 64 * WAVES;
   constexpr int ROWS = kFft / WAVES;
   static_assert(!RERANK || sizeof(T) == 4, "re-rank mode iterates in float");
@@ -395,8 +428,12 @@ __global__ __launch_bounds__(64 * WAVES) void fse_block_kernel(BlockArgs<T> a) {
   const int wave = uniform_int(tid >> 6);
   const int K = a.K;
 
-  const LdsLayout L = lds_layout(a.M, a.N, K, WAVES, (int)sizeof(T), !RERANK);
-  T* Wl = reinterpret_cast<T*>(smem);  // (64 + ROWS - 1) x 64 complex
+  // re-rank mode with 4 wavefronts: split rows, so that W with its
+  // wrap-around rows and the rest of the LDS fit four blocks on a CU
+  constexpr bool SPLIT = RERANK && WAVES == 4;
+  constexpr int WRAP = SPLIT ? ROWS / 2 - 1 : ROWS - 1;
+  const LdsLayout L = lds_layout(a.M, a.N, K, WAVES, (int)sizeof(T), !RERANK, WRAP);
+  T* Wl = reinterpret_cast<T*>(smem);  // (64 + WRAP) x 64 complex
   T* hdc = reinterpret_cast<T*>(smem + L.hist_dc);
   int* hu = reinterpret_cast<int*>(smem + L.hist_u);
   double* tw = reinterpret_cast<double*>(smem + L.tw64);
@@ -426,7 +463,7 @@ __global__ __launch_bounds__(64 * WAVES) void fse_block_kernel(BlockArgs<T> a) {
     if (W0d > 0.0) {
 #pragma unroll
       for (int j = 0; j < ROWS; ++j) {
-        const int k = (ROWS * wave + j) * kFft + lane;
+        const int k = row_of<WAVES, SPLIT>(wave, j) * kFft + lane;
         rr[j] = (T)spec[kSpecR0 + 2 * k];
         ri[j] = (T)spec[kSpecR0 + 2 * k + 1];
         wvr[j] = (T)spec[kSpecW + 2 * k];
@@ -443,11 +480,11 @@ __global__ __launch_bounds__(64 * WAVES) void fse_block_kernel(BlockArgs<T> a) {
   if (W0 > T(0)) {
 #pragma unroll
     for (int j = 0; j < ROWS; ++j) {
-      const int row = ROWS * wave + j;
+      const int row = row_of<WAVES, SPLIT>(wave, j);
       T* p = Wl + (row * kFft + lane) * 2;
       p[0] = wvr[j];
       p[1] = wvi[j];
-      if (row < ROWS - 1) {  // wrap-around copy: a wave's ROWS rows never wrap
+      if (row < WRAP) {  // wrap-around copy: a window of rows never wraps
         T* q = Wl + ((row + kFft) * kFft + lane) * 2;
         q[0] = wvr[j];
         q[1] = wvi[j];
@@ -472,15 +509,22 @@ __global__ __launch_bounds__(64 * WAVES) void fse_block_kernel(BlockArgs<T> a) {
     T dcr = T(0), dci = T(0);
     for (int it = 0; it < K; ++it) {
       const int col = (lane - (u & (kFft - 1))) & (kFft - 1);
-      const int b = uniform_int((ROWS * wave - (u >> 6)) & (kFft - 1));
+      const int b = uniform_int((row_of<WAVES, SPLIT>(wave, 0) - (u >> 6)) & (kFft - 1));
+      const int b2 = uniform_int((row_of<WAVES, SPLIT>(wave, ROWS / 2) - (u >> 6)) & (kFft - 1));
       const T* wp = Wl + (b * kFft + col) * 2;
+      const T* wp2 = Wl + (b2 * kFft + col) * 2;
       // all W reads of the iteration in flight before the first update, so
       // that one LDS latency is exposed per iteration instead of one per pair
       T wvr_[ROWS], wvi_[ROWS];
 #pragma unroll
       for (int j = 0; j < ROWS; ++j) {
-        wvr_[j] = wp[j * kFft * 2];
-        wvi_[j] = wp[j * kFft * 2 + 1];
+        if (SPLIT && j >= ROWS / 2) {
+          wvr_[j] = wp2[(j - ROWS / 2) * kFft * 2];
+          wvi_[j] = wp2[(j - ROWS / 2) * kFft * 2 + 1];
+        } else {
+          wvr_[j] = wp[j * kFft * 2];
+          wvi_[j] = wp[j * kFft * 2 + 1];
+        }
       }
       if constexpr (sizeof(T) == 4) __builtin_amdgcn_sched_barrier(0);
       VecR<T, ROWS> e;
@@ -500,7 +544,7 @@ __global__ __launch_bounds__(64 * WAVES) void fse_block_kernel(BlockArgs<T> a) {
         unsigned key[ROWS];
 #pragma unroll
         for (int j = 0; j < ROWS; ++j)
-          key[j] = pack_key(__float_as_uint(e[j]), (unsigned)(63 - (ROWS * wave + j)));
+          key[j] = pack_key(__float_as_uint(e[j]), (unsigned)(63 - row_of<WAVES, SPLIT>(wave, j)));
         unsigned lk = key[0];
 #pragma unroll
         for (int j = 1; j + 1 < ROWS; j += 2) lk = umax3(lk, key[j], key[j + 1]);
@@ -508,7 +552,7 @@ __global__ __launch_bounds__(64 * WAVES) void fse_block_kernel(BlockArgs<T> a) {
         const unsigned wk = wave_max(lk);
         const unsigned long long hit = __ballot(lk == wk);
         const int lw = uniform_int(__builtin_ctzll(hit));
-        const int jw = uniform_int(63 - (int)(wk & 63u) - ROWS * wave);
+        const int jw = uniform_int(j_of_row<WAVES, SPLIT>(63 - (int)(wk & 63u), wave));
         const T sr = read_lane((T)rr[jw], lw);
         const T si = read_lane((T)ri[jw], lw);
         int near = 0;
@@ -526,7 +570,7 @@ __global__ __launch_bounds__(64 * WAVES) void fse_block_kernel(BlockArgs<T> a) {
         if (lane == 0) {
           FSlot v;
           v.key = wk;
-          v.k = ((ROWS * wave + jw) << 6) | lw;
+          v.k = (row_of<WAVES, SPLIT>(wave, jw) << 6) | lw;
           v.re = sr;
           v.im = si;
           fs[wave] = v;
@@ -538,7 +582,7 @@ __global__ __launch_bounds__(64 * WAVES) void fse_block_kernel(BlockArgs<T> a) {
         // key), and its entry is taken from that lane
         const FSlot mine = fs[lane & (WAVES - 1)];
         const unsigned gk = group_max<WAVES>(mine.key);
-        const int wwin = uniform_int((63 - (int)(gk & 63u)) / ROWS);
+        const int wwin = uniform_int(wave_of_row<WAVES, SPLIT>(63 - (int)(gk & 63u)));
         u = uniform_int(__builtin_amdgcn_readlane(mine.k, wwin));
         dcr = gs * read_lane(mine.re, wwin);
         dci = gs * read_lane(mine.im, wwin);
@@ -561,7 +605,8 @@ __global__ __launch_bounds__(64 * WAVES) void fse_block_kernel(BlockArgs<T> a) {
               while (mm && nc < kCandWave) {
                 const int l = __builtin_ctzll(mm);
                 mm &= mm - 1;
-                packed |= (unsigned long long)(((ROWS * wave + j) << 6) | l) << (12 * nc);
+                packed |= (unsigned long long)((row_of<WAVES, SPLIT>(wave, j) << 6) | l)
+                          << (12 * nc);
                 ++nc;
               }
             }
@@ -575,13 +620,14 @@ __global__ __launch_bounds__(64 * WAVES) void fse_block_kernel(BlockArgs<T> a) {
                 r0i[c] = spec[kSpecR0 + 2 * kc + 1];
               }
             }
-            // history terms in rounds of 4 x 64 so that all gathers of a
+            // history terms in rounds of kRound x 64 so that all gathers of a
             // round are in flight together (one memory latency per round)
-            for (int i0 = 0; i0 < it; i0 += 256) {
-              double wr[4][kCandWave], wi[4][kCandWave];
-              int valid[4];
+            constexpr int kRound = 2;
+            for (int i0 = 0; i0 < it; i0 += 64 * kRound) {
+              double wr[kRound][kCandWave], wi[kRound][kCandWave];
+              int valid[kRound];
 #pragma unroll
-              for (int q = 0; q < 4; ++q) {
+              for (int q = 0; q < kRound; ++q) {
                 const int i = i0 + 64 * q + lane;
                 valid[q] = i < it;
                 const int uu = valid[q] ? hu[i] : 0;
@@ -598,7 +644,7 @@ __global__ __launch_bounds__(64 * WAVES) void fse_block_kernel(BlockArgs<T> a) {
                 }
               }
 #pragma unroll
-              for (int q = 0; q < 4; ++q) {
+              for (int q = 0; q < kRound; ++q) {
                 const int i = i0 + 64 * q + lane;
                 const double xr = valid[q] ? (double)hdc[2 * i] : 0.0;
                 const double xi = valid[q] ? (double)hdc[2 * i + 1] : 0.0;
@@ -817,7 +863,9 @@ static hipError_t launch_with_lds(K kernel, size_t& attr_bytes, int n_items, int
 template <typename T, int WAVES, bool RERANK>
 static hipError_t launch_block_w(const BlockArgs<T>& a, int n_items, hipStream_t s) {
   static size_t attr_bytes = 0;  // largest dynamic LDS size enabled so far
-  const size_t lds = (size_t)lds_bytes<T>(a.M, a.N, a.K, WAVES, !RERANK);
+  const size_t lds = (size_t)lds_bytes<T>(a.M, a.N, a.K, WAVES, !RERANK,
+                                          (RERANK && WAVES == 4) ? 64 / WAVES / 2 - 1
+                                                                 : 64 / WAVES - 1);
   return launch_with_lds(fse_block_kernel<T, WAVES, RERANK>, attr_bytes, n_items, 64 * WAVES,
                          lds, s, a);
 }

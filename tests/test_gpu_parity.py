@@ -367,6 +367,63 @@ def test_every_launch_shape_matches_oracle(monkeypatch, shape, precision):
         assert np.mean(errs <= FP32_TOL) >= 0.9
 
 
+# ------------------------------------------------------------ host buffers
+
+def _conceal_raw(plan, frames):
+    """fse_conceal_image through the C ABI with the given fse_frame fields:
+    (image, stride, lost, lost_stride, out, out_stride, width, height)."""
+    arr = (fse._Frame * len(frames))()
+    for c, (img, st, lost, lst, out, ost, W, H) in zip(arr, frames):
+        c.image, c.width, c.height, c.stride = img, W, H, st
+        c.lost, c.lost_stride, c.out, c.out_stride = lost, lst, out, ost
+        c.out_f32 = c.out_f64 = None
+        c.trace = None
+        c.stats = None
+    rc = plan._lib.fse_conceal_image(plan.handle, arr, len(frames))
+    assert rc == 0, plan._lib.fse_strerror(rc)
+
+
+@pytest.mark.parametrize("precision", [fse.FSE_FP32_RERANK, fse.FSE_FP64])
+def test_host_strides_and_aliased_output(precision):
+    """Host frames with row strides larger than the width (image, mask and
+    output each padded differently) and with the output aliasing the input
+    give the results of contiguous buffers, bit for bit; padding bytes are
+    left untouched."""
+    rng = np.random.default_rng(51)
+    shapes = [(70, 90), (33, 47), (128, 96)]
+    imgs = [synth.polygon_image(rng, H, W, radius=(8, 30)) for H, W in shapes]
+    losts = [synth.slice_loss(rng, H, W, 16, (0.2, 0.4)) for H, W in shapes]
+    p = fse.Params(border_d=14, iterations=40, precision=precision)
+    with fse.Plan(p) as plan:
+        ref = plan.fse_conceal_image(imgs, losts)
+        # padded strides
+        pads = []
+        raw = []
+        for im, lo in zip(imgs, losts):
+            H, W = im.shape
+            pi = np.full((H, W + 13), 7, np.uint8); pi[:, :W] = im
+            pl = np.full((H, W + 5), 3, np.uint8); pl[:, :W] = lo
+            po = np.full((H, W + 29), 201, np.uint8)
+            pads.append((pi, pl, po))
+            raw.append((pi.ctypes.data, pi.strides[0], pl.ctypes.data, pl.strides[0],
+                        po.ctypes.data, po.strides[0], W, H))
+        _conceal_raw(plan, raw)
+        for (pi, pl, po), r, im in zip(pads, ref, imgs):
+            W = im.shape[1]
+            np.testing.assert_array_equal(po[:, :W], r.out)
+            assert (po[:, W:] == 201).all()
+            assert (pi[:, W:] == 7).all() and (pl[:, W:] == 3).all()
+        # output aliasing the input image
+        alias = [np.ascontiguousarray(im).copy() for im in imgs]
+        lcont = [np.ascontiguousarray(lo) for lo in losts]
+        raw = [(a.ctypes.data, a.strides[0], lo.ctypes.data, lo.strides[0],
+                a.ctypes.data, a.strides[0], a.shape[1], a.shape[0])
+               for a, lo in zip(alias, lcont)]
+        _conceal_raw(plan, raw)
+        for a, r in zip(alias, ref):
+            np.testing.assert_array_equal(a, r.out)
+
+
 # ------------------------------------------------------------ frame groups
 
 @pytest.mark.parametrize("precision", [fse.FSE_FP64, fse.FSE_FP32_RERANK, fse.FSE_FP32])
