@@ -77,18 +77,27 @@ __host__ __device__ inline int64_t align16(int64_t v) { return (v + 15) & ~15LL;
 // `stage` = false for the re-rank iteration kernel, which receives its
 // spectra from the FP64 transform pass and needs no transform staging.
 __host__ __device__ inline LdsLayout lds_layout(int M, int N, int K, int waves, int tsize,
-                                                bool stage_needed = true, int wrap = -1) {
+                                                bool stage_needed = true) {
   LdsLayout L;
-  L.cs = 0;
   const int NP = N | 1;  // odd row pitch of the staged area
   const int rows = kFft / waves;
-  const int64_t stage_xw = 2LL * M * NP * tsize;
-  L.bx = stage_xw;
+  // staging: with 4 wavefronts the samples (T) and one weight class per
+  // sample, otherwise x and w (T each); then the row DFTs of x and w (M x 33
+  // complex each); the 64 x 64 complex exchange buffer of the column DFT
+  // reuses the region afterwards
+  if (waves == 4) {
+    L.cs = align16((int64_t)M * NP * tsize);
+    L.bx = align16(L.cs + (int64_t)M * NP);
+  } else {
+    L.cs = 0;
+    L.bx = 2LL * M * NP * tsize;
+  }
   L.bw = L.bx + (int64_t)M * kHalf * 2 * tsize;
   const int64_t stage = stage_needed ? L.bw + (int64_t)M * kHalf * 2 * tsize : 0;
-  // the W spectrum with `wrap` (default rows - 1) wrap-around rows (rows
-  // 64.. repeat 0..), so that a window of a wavefront's rows never wraps
-  if (wrap < 0) wrap = rows - 1;
+  // the W spectrum plus wrap-around rows (rows 64.. repeat 0..), so that a
+  // window of a wavefront's rows never wraps: windows of rows / 2 rows with 4
+  // wavefronts (split rows), of `rows` rows otherwise
+  const int wrap = waves == 4 ? rows / 2 - 1 : rows - 1;
   const int64_t wreg = (int64_t)(kFft + wrap) * kFft * 2 * tsize;
   const int64_t region = align16(stage > wreg ? stage : wreg);
   L.hist_dc = region;
@@ -127,9 +136,8 @@ __host__ __device__ inline LdsLayout dft_layout(int M, int N, int waves) {
 }
 
 template <typename T>
-inline int64_t lds_bytes(int M, int N, int K, int waves, bool stage_needed = true,
-                         int wrap = -1) {
-  return lds_layout(M, N, K, waves, (int)sizeof(T), stage_needed, wrap).total;
+inline int64_t lds_bytes(int M, int N, int K, int waves, bool stage_needed = true) {
+  return lds_layout(M, N, K, waves, (int)sizeof(T), stage_needed).total;
 }
 
 }  // namespace fse

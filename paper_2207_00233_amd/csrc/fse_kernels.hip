@@ -133,14 +133,47 @@ struct Slot {
   int k;        // its spectrum index k1 * 64 + k2
 };
 
+// Spectrum rows of wavefront `wave`: ROWS consecutive rows, or with SPLIT two
+// windows of ROWS/2 rows (w ROWS/2 .. and 32 + w ROWS/2 ..), which needs only
+// ROWS/2 - 1 wrap-around rows of W in LDS.
+template <int WAVES, bool SPLIT>
+__device__ __forceinline__ int row_of(int wave, int j) {
+  constexpr int ROWS = kFft / WAVES;
+  if constexpr (SPLIT)
+    return (j < ROWS / 2 ? 0 : kFft / 2 - ROWS / 2) + (ROWS / 2) * wave + j;
+  else
+    return ROWS * wave + j;
+}
+
+// Inverse of row_of: the wavefront that owns spectrum row `row`, and the
+// index j of that row in its registers.
+template <int WAVES, bool SPLIT>
+__device__ __forceinline__ int wave_of_row(int row) {
+  constexpr int ROWS = kFft / WAVES;
+  if constexpr (SPLIT)
+    return (row & (kFft / 2 - 1)) / (ROWS / 2);
+  else
+    return row / ROWS;
+}
+
+template <int WAVES, bool SPLIT>
+__device__ __forceinline__ int j_of_row(int row, int wave) {
+  constexpr int ROWS = kFft / WAVES;
+  if constexpr (SPLIT)
+    return (row & (kFft / 2 - 1)) - (ROWS / 2) * wave + (row >= kFft / 2 ? ROWS / 2 : 0);
+  else
+    return row - ROWS * wave;
+}
+
 // Phases A-C: gather and weight the area, transform, unpack.  Computes in T,
 // reads the working image in TI.  Returns W0 = sum of weights; when W0 > 0,
-// rr/ri hold X[k] and wvr/wvi hold W[k] for k1 = ROWS wave + j, k2 = lane.
+// rr/ri hold X[k] and wvr/wvi hold W[k] for k1 = row_of(wave, j), k2 = lane
+// (split rows with 4 wavefronts).  With 4 wavefronts (COMPACT) phase A stages
+// the samples as TI and one weight class per sample and phase B forms the
+// weights again from the radial table, which keeps the staging small enough
+// for several blocks per CU; otherwise phase A stages x and w themselves.
 // Ends with a barrier, after which the LDS region may be reused.
-// COMPACT: phase A stages the samples as TI and one weight class per sample
-// (the weights are formed again in phase B from the radial table), which
-// keeps the staging below the 64 x 64 complex exchange buffer.
-template <typename T, typename TI, int WAVES, bool COMPACT = false>
+template <typename T, typename TI, int WAVES>
 __device__ __forceinline__ T forward_transforms(unsigned char* smem, const LdsLayout& L, int M,
                                                 int N, const T* radial, T delta, T zscale,
                                                 const TI* img, const uint8_t* st, int H, int W,
@@ -151,9 +184,11 @@ __device__ __forceinline__ T forward_transforms(unsigned char* smem, const LdsLa
   constexpr int THREADS = 64 * WAVES;
   constexpr int ROWS = kFft / WAVES;
   constexpr int QB = (kHalf + WAVES - 1) / WAVES;  // row-DFT columns per wavefront
+  constexpr bool SPLIT = WAVES == 4;
+  constexpr bool COMPACT = WAVES == 4;
   const int tid = threadIdx.x;
   const int NP = N | 1;
-  T* xs = reinterpret_cast<T*>(smem);
+  T* xs = reinterpret_cast<T*>(smem);                     // x and w (full staging)
   T* ws = xs + M * NP;
   TI* fs = reinterpret_cast<TI*>(smem);                   // COMPACT: samples
   uint8_t* cs = reinterpret_cast<uint8_t*>(smem + L.cs);  // COMPACT: 0 none, 1 known, 2 recon
@@ -168,7 +203,7 @@ __device__ __forceinline__ T forward_transforms(unsigned char* smem, const LdsLa
   for (int i = tid; i < M * N; i += THREADS) {
     const int m = i / N, n = i - m * N;
     const int y = oy + m, x = ox + n;
-    T wv = T(0), xv = T(0);
+    T wv = T(0);
     TI f = TI(0);
     uint8_t c = 0;
     if (y >= 0 && y < H && x >= 0 && x < W) {
@@ -178,14 +213,13 @@ __device__ __forceinline__ T forward_transforms(unsigned char* smem, const LdsLa
       c = s == kKnown ? 1 : (s == kRecon ? 2 : 0);
       f = img[p];
       wv = radial[i] * fac;
-      xv = (T)f * wv;
     }
     if constexpr (COMPACT) {
       fs[m * NP + n] = f;
       cs[m * NP + n] = c;
     } else {
       ws[m * NP + n] = wv;
-      xs[m * NP + n] = xv;
+      xs[m * NP + n] = (T)f * wv;
     }
     wsum += wv;
   }
@@ -279,11 +313,11 @@ __device__ __forceinline__ T forward_transforms(unsigned char* smem, const LdsLa
       __syncthreads();
 #pragma unroll
       for (int j = 0; j < ROWS; ++j) {
-        const int k1 = ROWS * wave + j;
+        const int k1 = row_of<WAVES, SPLIT>(wave, j);
         T ar = T(0), ai = T(0);
 #pragma unroll
         for (int m0 = 0; m0 < 4; ++m0) {
-          const T* p = Zl + ((m0 * ROWS + j) * kFft + lane) * 2;
+          const T* p = Zl + ((m0 * ROWS + (k1 & (ROWS - 1))) * kFft + lane) * 2;
           const T yr = p[0], yi = p[1];
           const int t = (m0 * k1) & (kFft - 1);
           const T cc = twt[2 * t], ss = twt[2 * t + 1];
@@ -299,7 +333,7 @@ __device__ __forceinline__ T forward_transforms(unsigned char* smem, const LdsLa
         zval(m, zr, zi);
 #pragma unroll
         for (int j = 0; j < ROWS; ++j) {
-          const int t = ((ROWS * wave + j) * m) & (kFft - 1);
+          const int t = (row_of<WAVES, SPLIT>(wave, j) * m) & (kFft - 1);
           const T cc = twt[2 * t], ss = twt[2 * t + 1];
           rr[j] = fma(zr, cc, fma(zi, ss, rr[j]));
           ri[j] = fma(zi, cc, fma(-zr, ss, ri[j]));
@@ -310,7 +344,7 @@ __device__ __forceinline__ T forward_transforms(unsigned char* smem, const LdsLa
   __syncthreads();  // phase-B buffers (and the partial DFTs) are dead from here on
 #pragma unroll
   for (int j = 0; j < ROWS; ++j) {
-    T* p = Zl + ((ROWS * wave + j) * kFft + lane) * 2;
+    T* p = Zl + (row_of<WAVES, SPLIT>(wave, j) * kFft + lane) * 2;
     p[0] = rr[j];
     p[1] = ri[j];
   }
@@ -320,7 +354,7 @@ __device__ __forceinline__ T forward_transforms(unsigned char* smem, const LdsLa
     const T h = T(0.5), hs = T(0.5) / zscale;
 #pragma unroll
     for (int j = 0; j < ROWS; ++j) {
-      const int k1 = ROWS * wave + j;
+      const int k1 = row_of<WAVES, SPLIT>(wave, j);
       const T* p = Zl + ((((kFft - k1) & (kFft - 1)) * kFft) + ((kFft - lane) & (kFft - 1))) * 2;
       const T pr = p[0], pi = p[1];
       const T ar = rr[j], ai = ri[j];
@@ -365,7 +399,7 @@ __global__ __launch_bounds__(64 * WAVES) void fse_dft64_kernel(BlockArgs<float> 
   load_twiddles<double>(smem, L, a.twid64);
   VecR<double, ROWS> rr, ri;
   double wvr[ROWS], wvi[ROWS];
-  const double W0 = forward_transforms<double, float, WAVES, true>(
+  const double W0 = forward_transforms<double, float, WAVES>(
       smem, L, a.M, a.N, radial64, a.delta64, 128.0, a.work + fd.off, a.state + fd.off,
       fd.H, fd.W, by0 - a.d, bx0 - a.d, lane, wave, rr, ri, wvr, wvi);
   double* out = a.spec64 + (int64_t)item * kSpecStride;
@@ -373,45 +407,13 @@ __global__ __launch_bounds__(64 * WAVES) void fse_dft64_kernel(BlockArgs<float> 
   if (W0 > 0.0) {
 #pragma unroll
     for (int j = 0; j < ROWS; ++j) {
-      const int k = (ROWS * wave + j) * kFft + lane;
+      const int k = row_of<WAVES, WAVES == 4>(wave, j) * kFft + lane;
       out[kSpecR0 + 2 * k] = rr[j];
       out[kSpecR0 + 2 * k + 1] = ri[j];
       out[kSpecW + 2 * k] = wvr[j];
       out[kSpecW + 2 * k + 1] = wvi[j];
     }
   }
-}
-
-// Spectrum rows of wavefront `wave`: ROWS consecutive rows, or with SPLIT two
-// windows of ROWS/2 rows (w ROWS/2 .. and 32 + w ROWS/2 ..), which needs only
-// ROWS/2 - 1 wrap-around rows of W in LDS.
-template <int WAVES, bool SPLIT>
-__device__ __forceinline__ int row_of(int wave, int j) {
-  constexpr int ROWS = kFft / WAVES;
-  if constexpr (SPLIT)
-    return (j < ROWS / 2 ? 0 : kFft / 2 - ROWS / 2) + (ROWS / 2) * wave + j;
-  else
-    return ROWS * wave + j;
-}
-
-// Inverse of row_of: the wavefront that owns spectrum row `row`, and the
-// index j of that row in its registers.
-template <int WAVES, bool SPLIT>
-__device__ __forceinline__ int wave_of_row(int row) {
-  constexpr int ROWS = kFft / WAVES;
-  if constexpr (SPLIT)
-    return (row & (kFft / 2 - 1)) / (ROWS / 2);
-  else
-    return row / ROWS;
-}
-
-template <int WAVES, bool SPLIT>
-__device__ __forceinline__ int j_of_row(int row, int wave) {
-  constexpr int ROWS = kFft / WAVES;
-  if constexpr (SPLIT)
-    return (row & (kFft / 2 - 1)) - (ROWS / 2) * wave + (row >= kFft / 2 ? ROWS / 2 : 0);
-  else
-    return row - ROWS * wave;
 }
 
 // RERANK (T = float only): spectra come from fse_dft64_kernel, and near-tied
@@ -428,11 +430,11 @@ __global__ __launch_bounds__(64 * WAVES, (RERANK && WAVES == 4) ? 4 : 1) void fs
   const int wave = uniform_int(tid >> 6);
   const int K = a.K;
 
-  // re-rank mode with 4 wavefronts: split rows, so that W with its
-  // wrap-around rows and the rest of the LDS fit four blocks on a CU
-  constexpr bool SPLIT = RERANK && WAVES == 4;
+  // 4 wavefronts: split rows, so that W with its wrap-around rows and the
+  // rest of the LDS take at most a quarter of a CU's LDS (FP32)
+  constexpr bool SPLIT = WAVES == 4;
   constexpr int WRAP = SPLIT ? ROWS / 2 - 1 : ROWS - 1;
-  const LdsLayout L = lds_layout(a.M, a.N, K, WAVES, (int)sizeof(T), !RERANK, WRAP);
+  const LdsLayout L = lds_layout(a.M, a.N, K, WAVES, (int)sizeof(T), !RERANK);
   T* Wl = reinterpret_cast<T*>(smem);  // (64 + WRAP) x 64 complex
   T* hdc = reinterpret_cast<T*>(smem + L.hist_dc);
   int* hu = reinterpret_cast<int*>(smem + L.hist_u);
@@ -720,16 +722,22 @@ __global__ __launch_bounds__(64 * WAVES, (RERANK && WAVES == 4) ? 4 : 1) void fs
           v.e = wm;
           v.re = sr;
           v.im = si;
-          v.k = ((ROWS * wave + jw) << 6) | lw;
+          v.k = (row_of<WAVES, SPLIT>(wave, jw) << 6) | lw;
           sl[wave] = v;
         }
         __syncthreads();
-        // wavefronts cover increasing k, so a strict > keeps the smallest k
+        // the largest |R|^2, ties to the smallest index k: consecutive rows
+        // per wavefront cover increasing k, so a strict > keeps the smallest;
+        // split rows compare the indices
         Slot best = sl[0];
 #pragma unroll
         for (int q = 1; q < WAVES; ++q) {
           const Slot c = sl[q];
-          if (c.e > best.e) best = c;
+          if constexpr (SPLIT) {
+            if (c.e > best.e || (c.e == best.e && c.k < best.k)) best = c;
+          } else {
+            if (c.e > best.e) best = c;
+          }
         }
         u = uniform_int(best.k);
         dcr = gs * (T)best.re;
@@ -863,9 +871,7 @@ static hipError_t launch_with_lds(K kernel, size_t& attr_bytes, int n_items, int
 template <typename T, int WAVES, bool RERANK>
 static hipError_t launch_block_w(const BlockArgs<T>& a, int n_items, hipStream_t s) {
   static size_t attr_bytes = 0;  // largest dynamic LDS size enabled so far
-  const size_t lds = (size_t)lds_bytes<T>(a.M, a.N, a.K, WAVES, !RERANK,
-                                          (RERANK && WAVES == 4) ? 64 / WAVES / 2 - 1
-                                                                 : 64 / WAVES - 1);
+  const size_t lds = (size_t)lds_bytes<T>(a.M, a.N, a.K, WAVES, !RERANK);
   return launch_with_lds(fse_block_kernel<T, WAVES, RERANK>, attr_bytes, n_items, 64 * WAVES,
                          lds, s, a);
 }
