@@ -110,6 +110,37 @@ __device__ __forceinline__ unsigned umax3(unsigned a, unsigned b, unsigned c) {
   return max(a, max(b, c));
 }
 
+// Median of three (v_med3_u32).
+__device__ __forceinline__ unsigned umed3(unsigned a, unsigned b, unsigned c) {
+  return max(min(a, b), min(max(a, b), c));
+}
+
+// Largest (m1) and second largest (m2) of N distinct keys: triples by
+// max3/med3, then merges, top2 of two pairs being med3(m1, n1, max(m2, n2)).
+template <int N>
+__device__ __forceinline__ void top2(const unsigned (&k)[N], unsigned& m1, unsigned& m2) {
+  m1 = k[0];
+  m2 = 0u;
+  int j = 1;
+  if constexpr (N >= 3) {
+    m1 = umax3(k[0], k[1], k[2]);
+    m2 = umed3(k[0], k[1], k[2]);
+    j = 3;
+  }
+#pragma unroll
+  for (; j + 2 < N; j += 3) {
+    const unsigned n1 = umax3(k[j], k[j + 1], k[j + 2]);
+    const unsigned n2 = umed3(k[j], k[j + 1], k[j + 2]);
+    m2 = umed3(m1, n1, max(m2, n2));
+    m1 = max(m1, n1);
+  }
+#pragma unroll
+  for (; j < N; ++j) {
+    m2 = umed3(m1, k[j], m2);
+    m1 = max(m1, k[j]);
+  }
+}
+
 // (bits & ~63) | (low & 63) as one bit-field insert (the compiler otherwise
 // splits it into two operations).
 __device__ __forceinline__ unsigned pack_key(unsigned bits, unsigned low) {
@@ -547,10 +578,15 @@ __global__ __launch_bounds__(64 * WAVES, (RERANK && WAVES == 4) ? 4 : 1) void fs
 #pragma unroll
         for (int j = 0; j < ROWS; ++j)
           key[j] = pack_key(__float_as_uint(e[j]), (unsigned)(63 - row_of<WAVES, SPLIT>(wave, j)));
-        unsigned lk = key[0];
+        unsigned lk, lk2 = 0u;
+        if constexpr (RERANK) {
+          top2<ROWS>(key, lk, lk2);  // lk2 tests a second near entry in the lane
+        } else {
+          lk = key[0];
 #pragma unroll
-        for (int j = 1; j + 1 < ROWS; j += 2) lk = umax3(lk, key[j], key[j + 1]);
-        if constexpr (ROWS % 2 == 0) lk = max(lk, key[ROWS - 1]);
+          for (int j = 1; j + 1 < ROWS; j += 2) lk = umax3(lk, key[j], key[j + 1]);
+          if constexpr (ROWS % 2 == 0) lk = max(lk, key[ROWS - 1]);
+        }
         const unsigned wk = wave_max(lk);
         const unsigned long long hit = __ballot(lk == wk);
         const int lw = uniform_int(__builtin_ctzll(hit));
@@ -559,12 +595,14 @@ __global__ __launch_bounds__(64 * WAVES, (RERANK && WAVES == 4) ? 4 : 1) void fs
         const T si = read_lane((T)ri[jw], lw);
         int near = 0;
         if constexpr (RERANK) {
-          // entries within the gap of this wavefront's maximum (conservative:
-          // the block maximum is at least as large)
+          // 2 when another entry of this wavefront lies within the gap of its
+          // maximum (another lane's maximum, or a lane's second largest key),
+          // else 1 (conservative: the block maximum is at least as large)
           const float lim = __uint_as_float(wk) * (float)(1.0 - a.rerank_gap);
           const unsigned thr = __float_as_uint(lim);
-#pragma unroll
-          for (int j = 0; j < ROWS; ++j) near += __builtin_popcountll(__ballot(key[j] >= thr));
+          const bool two = __ballot(lk2 >= thr) != 0ull ||
+                           __builtin_popcountll(__ballot(lk >= thr)) >= 2;
+          near = two ? 2 : 1;
         }
         FSlot* fs = reinterpret_cast<FSlot*>(smem + L.slots) + (it & 1) * WAVES;
         int* nr = reinterpret_cast<int*>(smem + L.slots + 2 * WAVES * sizeof(FSlot)) +
