@@ -2,9 +2,13 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+#include <condition_variable>
 #include <cstddef>
 #include <cstdint>
+#include <functional>
 #include <mutex>
+#include <thread>
 #include <vector>
 
 #include "fse.h"
@@ -27,6 +31,28 @@ struct HostBuf {
   void release();
 };
 
+// Persistent host worker threads of a plan: run(n, fn) calls fn(0..n-1) on the
+// workers and the calling thread and returns when all calls have returned.
+// One run at a time (the plan serializes its synchronous calls).
+class HostPool {
+ public:
+  explicit HostPool(int workers);
+  ~HostPool();
+  void run(int n, const std::function<void(int)>& fn);
+
+ private:
+  void worker();
+  std::vector<std::thread> th_;
+  std::mutex mu_;
+  std::condition_variable cv_, done_cv_;
+  const std::function<void(int)>* fn_ = nullptr;
+  int n_ = 0;
+  std::atomic<int> next_{0};
+  int active_ = 0;
+  uint64_t gen_ = 0;
+  bool stop_ = false;
+};
+
 struct Serving;
 
 int validate_params(const fse_params* p);
@@ -46,6 +72,7 @@ struct fse_plan_s {
   fse::DevBuf work, state, frames_dev, items_dev, u8_img, u8_lost, u8_out, fout, staging,
       trace_u, trace_dc, flags_dev, io_dev;
   fse::HostBuf pin_in, pin_out;  // pinned staging of host frames (inputs, 8-bit outputs)
+  fse::HostPool* pool = nullptr;  // host workers (scheduling, host frame copies)
   std::vector<hipEvent_t> events;
   // wavefronts per block by launch size: at most wide_threshold blocks -> 16,
   // at most mid_threshold -> 8, else 4 (fewer blocks than the GPU holds leave

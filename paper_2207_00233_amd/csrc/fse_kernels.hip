@@ -856,14 +856,17 @@ template <typename T>
 __global__ void fse_init_kernel(const IoDesc* io, T* work, uint8_t* state, uint8_t* flags,
                                 int Bh, int Bw, int gox, int goy) {
   const IoDesc d = io[blockIdx.y];
-  const int64_t n = (int64_t)d.H * d.W;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int y = (int)(i / d.W), x = (int)(i - (int64_t)y * d.W);
-    const bool l = d.lost[(int64_t)y * d.lstride + x] != 0;
-    work[d.off + i] = l ? T(0) : (T)d.image[(int64_t)y * d.stride + x];
-    state[d.off + i] = l ? kPending : kKnown;
-    if (l && flags) flags[d.flag_off + (int64_t)((y + goy) / Bh) * d.wb + (x + gox) / Bw] = 1;
+  for (int y = blockIdx.x; y < d.H; y += gridDim.x) {  // rows; lanes along the row
+    const uint8_t* lr = d.lost + (int64_t)y * d.lstride;
+    const uint8_t* ir = d.image + (int64_t)y * d.stride;
+    const int64_t o = d.off + (int64_t)y * d.W;
+    uint8_t* fr = flags ? flags + d.flag_off + (int64_t)((y + goy) / Bh) * d.wb : nullptr;
+    for (int x = threadIdx.x; x < d.W; x += blockDim.x) {
+      const bool l = lr[x] != 0;
+      work[o + x] = l ? T(0) : (T)ir[x];
+      state[o + x] = l ? kPending : kKnown;
+      if (l && fr) fr[(x + gox) / Bw] = 1;
+    }
   }
 }
 
@@ -872,22 +875,25 @@ __global__ void fse_init_kernel(const IoDesc* io, T* work, uint8_t* state, uint8
 template <typename T>
 __global__ void fse_finalize_kernel(const IoDesc* io, const uint8_t* state, const T* work) {
   const IoDesc d = io[blockIdx.y];
-  const int64_t n = (int64_t)d.H * d.W;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int y = (int)(i / d.W), x = (int)(i - (int64_t)y * d.W);
-    const T v = work[d.off + i];
-    uint8_t o;
-    if (state[d.off + i] == kKnown) {
-      o = d.image[(int64_t)y * d.stride + x];
-    } else {
-      T r = rint(v);
-      r = r < T(0) ? T(0) : (r > T(255) ? T(255) : r);
-      o = (uint8_t)r;
+  for (int y = blockIdx.x; y < d.H; y += gridDim.x) {  // rows; lanes along the row
+    const int64_t o = d.off + (int64_t)y * d.W;
+    const int64_t oi = (int64_t)y * d.W;
+    const uint8_t* ir = d.image + (int64_t)y * d.stride;
+    uint8_t* outr = d.out + (int64_t)y * d.ostride;
+    for (int x = threadIdx.x; x < d.W; x += blockDim.x) {
+      const T v = work[o + x];
+      uint8_t b;
+      if (state[o + x] == kKnown) {
+        b = ir[x];
+      } else {
+        T r = rint(v);
+        r = r < T(0) ? T(0) : (r > T(255) ? T(255) : r);
+        b = (uint8_t)r;
+      }
+      outr[x] = b;
+      if (d.of32) d.of32[oi + x] = (float)v;
+      if (d.of64) d.of64[oi + x] = (double)v;
     }
-    d.out[(int64_t)y * d.ostride + x] = o;
-    if (d.of32) d.of32[i] = (float)v;
-    if (d.of64) d.of64[i] = (double)v;
   }
 }
 
@@ -972,9 +978,12 @@ hipError_t launch_scatter(T* work, uint8_t* state, const FrameDesc* frames, cons
   return hipGetLastError();
 }
 
-static int grid_for(int64_t n) {
-  int64_t g = (n + 255) / 256;
-  if (g > 2048) g = 2048;
+// Workgroups per frame of the init and finalize kernels: one row each, at
+// most 256 (a workgroup strides over the rows), at least enough for the
+// largest frame's rows at 64 pixels per row.
+static int grid_rows(int64_t max_pixels) {
+  int64_t g = (max_pixels + 4095) / 4096;
+  if (g > 256) g = 256;
   return (int)(g < 1 ? 1 : g);
 }
 
@@ -982,7 +991,7 @@ template <typename T>
 hipError_t launch_init(const IoDesc* io, int nframes, int64_t max_pixels, T* work,
                        uint8_t* state, uint8_t* flags, int Bh, int Bw, int gox, int goy,
                        hipStream_t s) {
-  hipLaunchKernelGGL(fse_init_kernel<T>, dim3(grid_for(max_pixels), nframes), dim3(256), 0, s,
+  hipLaunchKernelGGL(fse_init_kernel<T>, dim3(grid_rows(max_pixels), nframes), dim3(256), 0, s,
                      io, work, state, flags, Bh, Bw, gox, goy);
   return hipGetLastError();
 }
@@ -990,7 +999,7 @@ hipError_t launch_init(const IoDesc* io, int nframes, int64_t max_pixels, T* wor
 template <typename T>
 hipError_t launch_finalize(const IoDesc* io, int nframes, int64_t max_pixels,
                            const uint8_t* state, const T* work, hipStream_t s) {
-  hipLaunchKernelGGL(fse_finalize_kernel<T>, dim3(grid_for(max_pixels), nframes), dim3(256), 0,
+  hipLaunchKernelGGL(fse_finalize_kernel<T>, dim3(grid_rows(max_pixels), nframes), dim3(256), 0,
                      s, io, state, work);
   return hipGetLastError();
 }

@@ -171,21 +171,66 @@ int plan_device_init(fse_plan_s* pl) {
 
 // ------------------------------------------------------------ batch execution
 
-// fn(0..n-1) on up to 16 host threads.
-template <typename F>
-static void parallel_for(int n, F&& fn) {
-  const int nt = std::min<int>(n, std::min(16u, std::max(1u, std::thread::hardware_concurrency())));
-  if (nt <= 1) {
+HostPool::HostPool(int workers) {
+  for (int t = 0; t < workers; ++t) th_.emplace_back([this] { worker(); });
+}
+
+HostPool::~HostPool() {
+  {
+    std::lock_guard<std::mutex> lk(mu_);
+    stop_ = true;
+  }
+  cv_.notify_all();
+  for (auto& t : th_) t.join();
+}
+
+void HostPool::worker() {
+  uint64_t seen = 0;
+  for (;;) {
+    const std::function<void(int)>* fn;
+    int n;
+    {
+      std::unique_lock<std::mutex> lk(mu_);
+      cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+      if (stop_) return;
+      seen = gen_;
+      fn = fn_;
+      n = n_;
+    }
+    for (int i = next_++; i < n; i = next_++) (*fn)(i);
+    std::lock_guard<std::mutex> lk(mu_);
+    if (--active_ == 0) done_cv_.notify_all();
+  }
+}
+
+void HostPool::run(int n, const std::function<void(int)>& fn) {
+  if (th_.empty() || n <= 1) {
     for (int i = 0; i < n; ++i) fn(i);
     return;
   }
-  std::atomic<int> next{0};
-  std::vector<std::thread> pool;
-  for (int t = 0; t < nt; ++t)
-    pool.emplace_back([&] {
-      for (int i = next++; i < n; i = next++) fn(i);
-    });
-  for (auto& th : pool) th.join();
+  {
+    std::lock_guard<std::mutex> lk(mu_);
+    fn_ = &fn;
+    n_ = n;
+    next_ = 0;
+    active_ = (int)th_.size();
+    ++gen_;
+  }
+  cv_.notify_all();
+  for (int i = next_++; i < n; i = next_++) fn(i);
+  std::unique_lock<std::mutex> lk(mu_);
+  done_cv_.wait(lk, [&] { return active_ == 0; });
+  fn_ = nullptr;
+}
+
+// fn(0..n-1) on the plan's host workers (created on first use: up to 15
+// threads besides the caller).
+static void parallel_for(fse_plan_s* pl, int n, const std::function<void(int)>& fn) {
+  if (!pl->pool) {
+    const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+    pl->pool = new HostPool(std::min(15, hw - 1));
+  }
+  pl->pool->run(n, fn);
 }
 
 // Group 0 runs on the plan's stream; groups 1.. on non-blocking streams of
@@ -256,7 +301,7 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
     // arena (pageable 2-D copies would go row by row)
     uint8_t* pimg = (uint8_t*)pl->pin_in.ptr;
     uint8_t* plost = pimg + total;
-    parallel_for(n, [&](int f) {
+    parallel_for(pl, n, [&](int f) {
       const fse_frame& fr = frames[f];
       const int H = fr.height, W = fr.width;
       uint8_t* a = pimg + fd[f].off;
@@ -312,26 +357,12 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
 
   // processing order per frame
   std::vector<std::vector<int32_t>> wave_of(n), seq(n);
-  // frames are scheduled independently, on up to 16 host threads
+  // frames are scheduled independently, on the plan's host workers
   std::vector<int> nwaves(n, 0);
-  {
-    auto run = [&](int f) {
-      wave_of[f].resize((size_t)hb[f] * wb[f]);
-      nwaves[f] = schedule_blocks(hb[f], wb[f], flags[f], p.order, wave_of[f].data(), &seq[f]);
-    };
-    const int nt = std::min<int>(n, std::min(16u, std::max(1u, std::thread::hardware_concurrency())));
-    if (nt <= 1) {
-      for (int f = 0; f < n; ++f) run(f);
-    } else {
-      std::atomic<int> next{0};
-      std::vector<std::thread> pool;
-      for (int t = 0; t < nt; ++t)
-        pool.emplace_back([&] {
-          for (int f = next++; f < n; f = next++) run(f);
-        });
-      for (auto& th : pool) th.join();
-    }
-  }
+  parallel_for(pl, n, [&](int f) {
+    wave_of[f].resize((size_t)hb[f] * wb[f]);
+    nwaves[f] = schedule_blocks(hb[f], wb[f], flags[f], p.order, wave_of[f].data(), &seq[f]);
+  });
   for (int f = 0; f < n; ++f) {
     const int nw = nwaves[f];
     if (frames[f].stats) {
@@ -542,7 +573,7 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
   if ((rc = chk(hipStreamSynchronize(s)))) return rc;
   if (!dev) {
     const uint8_t* pout = (const uint8_t*)pl->pin_out.ptr;
-    parallel_for(n, [&](int f) {
+    parallel_for(pl, n, [&](int f) {
       const fse_frame& fr = frames[f];
       for (int y = 0; y < fr.height; ++y)
         std::memcpy(fr.out + (int64_t)y * fr.out_stride, pout + fd[f].off + (int64_t)y * fr.width,
@@ -715,6 +746,8 @@ int32_t fse_plan_destroy(fse_plan_t pl) {
   for (DevBuf* b : bufs) b->release();
   pl->pin_in.release();
   pl->pin_out.release();
+  delete pl->pool;
+  pl->pool = nullptr;
   if (pl->own_stream && pl->stream) (void)hipStreamDestroy(pl->stream);
   delete pl;
   return FSE_OK;
