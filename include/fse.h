@@ -135,10 +135,17 @@ typedef struct {
  * Errors: FSE_ERR_INVALID (p or out null, parameter out of range,
  * block + 2d > fft), FSE_ERR_UNSUPPORTED (fft other than 64 x 64),
  * FSE_ERR_DEVICE (no usable device).  On error *out is set to NULL.
- * Tuning: the environment variable FSE_WAVE_THRESHOLDS="t16,t8", read here,
+ * Tuning: environment variables read here.  FSE_WAVE_THRESHOLDS="t16,t8"
  * sets the launch sizes (blocks per launch) up to which a block runs on 16
  * or on 8 wavefronts instead of 4; results equal the oracle's to the same
  * tolerance in every shape, not bit for bit across shapes.
+ * FSE_FRAME_GROUPS=g (1..16) sets the number of frame groups of a batched
+ * call (default 3 in FSE_FP32_RERANK, else 2).  FSE_CRIT_DEPTH=c (0..1):
+ * frames whose schedule has at least c times the waves of the deepest frame
+ * form a group of their own with the launch shape of their own size and a
+ * raised wave priority (FSE_CRIT_PRIO=0 keeps the default priority); 0 = off,
+ * default 0.9 in FSE_FP32_RERANK, else off.  None of these changes results
+ * beyond the per-shape rounding noted above.
  */
 int32_t fse_plan(const fse_params *p, void *hip_stream, fse_plan_t *out);
 
@@ -153,9 +160,9 @@ int32_t fse_plan_destroy(fse_plan_t plan);
  * it gets alone.  With FSE_FLAG_DEVICE_PTRS, image/lost/out/out_f32/out_f64
  * are device pointers and the work is ordered on the plan's stream; the call
  * still returns only when the result is complete.
- * Errors: FSE_ERR_INVALID (null plan/frames/pointers, n < 1, sizes <= 0 or
- * above 65535, strides smaller than width, a trace with device pointers),
- * FSE_ERR_DEVICE.
+ * Errors: FSE_ERR_INVALID (null plan/frames/pointers, n < 1 or above
+ * 16777215, sizes <= 0 or above 65535, strides smaller than width, a trace
+ * with device pointers), FSE_ERR_DEVICE.
  */
 int32_t fse_conceal_image(fse_plan_t plan, const fse_frame *frames, int32_t n);
 

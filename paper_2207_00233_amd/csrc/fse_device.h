@@ -35,7 +35,7 @@ struct BlockArgs {
   T* work;                 // working image arena (values of every frame)
   uint8_t* state;          // state arena (kKnown / kPending / kRecon)
   const FrameDesc* frames;
-  const int32_t* items;    // 2 ints per work item: frame, (bi << 16) | bj
+  const int32_t* items;    // 2 ints per work item: frame | priority << 24, (bi << 16) | bj
   const T* radial;         // M*N table rho^dist of Eq. (2)
   const T* twid;           // 64 x (cos, sin)(2 pi t / 64) in T
   const double* twid64;    // 64 x (cos, sin)(2 pi t / 64) in double
@@ -49,6 +49,12 @@ struct BlockArgs {
   double* spec64;          // FP64 spectra per work item (re-rank mode), see below
   double rerank_gap;       // relative |R|^2 gap that triggers an FP64 re-rank
 };
+
+// Work item encoding: the first int holds the frame index in its low 24 bits
+// and, above them, a flag that raises the wave priority of the item's
+// workgroup (items on a batch's critical chain of waves).
+constexpr int32_t kItemFrameMask = 0xffffff;
+constexpr int kItemPrioShift = 24;
 
 // FP64 spectra of one work item written by the FP64 transform pass of the
 // re-rank mode: R0 (64 x 64 complex), W (64 x 64 complex), then W0.
@@ -104,7 +110,8 @@ __host__ __device__ inline LdsLayout lds_layout(int M, int N, int K, int waves, 
   L.hist_u = L.hist_dc + (int64_t)K * 2 * tsize;
   L.tw64 = align16(L.hist_u + (int64_t)K * 4);
   L.twt = L.tw64 + kFft * 2 * 8;
-  L.slots = align16(L.twt + kFft * 2 * tsize);
+  // the T twiddles serve the transforms only
+  L.slots = align16(L.twt + (stage_needed ? kFft * 2 * tsize : 0));
   L.cand = L.slots + 2LL * waves * 32;
   L.misc = L.cand + 2LL * waves * 32;
   L.misc = align16(L.misc);

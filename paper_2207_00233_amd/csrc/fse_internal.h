@@ -91,6 +91,19 @@ struct fse_plan_s {
   int group_count() const {
     return groups > 0 ? groups : (p.precision == FSE_FP32_RERANK ? 3 : 2);
   }
+  // frames whose schedule has at least crit_depth() x the waves of the
+  // deepest frame of a batch form group 0 (when there are other frames): their
+  // chain of waves bounds the batch, so their launches take the wavefront
+  // count of their own size (small launches -> 16 wavefronts, shorter
+  // iterations) instead of the step total's, and their workgroups raise their
+  // wave priority (crit_prio).  0 = off; < 0 = by precision, measured on
+  // MI355X with the 64-frame batch: 0.9 for the re-rank mode, whose per-step
+  // transform pass lengthens the chain, else off
+  double crit = -1.0;
+  double crit_depth() const {
+    return crit >= 0.0 ? crit : (p.precision == FSE_FP32_RERANK ? 0.9 : 0.0);
+  }
+  bool crit_prio = true;
   std::vector<hipStream_t> gstreams;
   std::vector<hipEvent_t> gjoin;
   // launch cost model used to stagger frames: max(latency, blocks / rate),

@@ -24,6 +24,8 @@
 // fill the GPU.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "fse_device.h"
 
 namespace fse {
@@ -76,6 +78,40 @@ __device__ __forceinline__ double dpp_max_step(double x) {
   int yhi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWMASK, 0xF, false);
   double y = __longlong_as_double(((long long)yhi << 32) | (unsigned int)ylo);
   return fmax(x, y);
+}
+
+// One DPP step of a wavefront sum in double: x += x moved by CTRL (a lane
+// without a source adds its own value; only lane 63's sum is used below).
+template <int CTRL>
+__device__ __forceinline__ double dpp_add_step(double x) {
+  long long b = __double_as_longlong(x);
+  int lo = (int)(b & 0xffffffffLL), hi = (int)(b >> 32);
+  int ylo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xF, 0xF, false);
+  int yhi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, false);
+  return x + __longlong_as_double(((long long)yhi << 32) | (unsigned int)ylo);
+}
+
+// Wavefront sums of C values at once (the C reduction trees interleave),
+// returned uniform.  Quads, then rows of 16 (every lane of a row ends with
+// the row sum), then row 1 += row 0 and row 3 += row 2 (row_bcast:15), then
+// row 3 += row 1 (row_bcast:31): lane 63 holds the wavefront sum.  Lanes
+// outside rows 1 and 3 collect partial sums that are not read.
+template <int C>
+__device__ __forceinline__ void wave_sums(double (&x)[C]) {
+#pragma unroll
+  for (int c = 0; c < C; ++c) x[c] = dpp_add_step<0xB1>(x[c]);   // quad_perm [1,0,3,2]
+#pragma unroll
+  for (int c = 0; c < C; ++c) x[c] = dpp_add_step<0x4E>(x[c]);   // quad_perm [2,3,0,1]
+#pragma unroll
+  for (int c = 0; c < C; ++c) x[c] = dpp_add_step<0x124>(x[c]);  // row_ror:4
+#pragma unroll
+  for (int c = 0; c < C; ++c) x[c] = dpp_add_step<0x128>(x[c]);  // row_ror:8
+#pragma unroll
+  for (int c = 0; c < C; ++c) x[c] = dpp_add_step<0x142>(x[c]);  // row_bcast:15
+#pragma unroll
+  for (int c = 0; c < C; ++c) x[c] = dpp_add_step<0x143>(x[c]);  // row_bcast:31
+#pragma unroll
+  for (int c = 0; c < C; ++c) x[c] = read_lane(x[c], 63);
 }
 
 // Wavefront maximum (exact: max is order-free), returned uniform.
@@ -152,7 +188,7 @@ __device__ __forceinline__ unsigned pack_key(unsigned bits, unsigned low) {
 // Argmax slot of the FP32 iteration (16 bytes): the wavefront's best entry.
 struct FSlot {
   unsigned key;  // packed selection key
-  int k;         // spectrum index k1 * 64 + k2
+  int k;         // spectrum index k1 * 64 + k2; re-rank: near-tie count << 12
   float re, im;  // residual value
 };
 
@@ -402,12 +438,12 @@ __device__ __forceinline__ T forward_transforms(unsigned char* smem, const LdsLa
 // Twiddle tables into LDS (double for the synthesis, T for the transforms).
 template <typename T>
 __device__ __forceinline__ void load_twiddles(unsigned char* smem, const LdsLayout& L,
-                                              const double* twid64) {
+                                              const double* twid64, bool with_t = true) {
   const int tid = threadIdx.x;
   if (tid < 2 * kFft) {
     const double v = twid64[tid];
     reinterpret_cast<double*>(smem + L.tw64)[tid] = v;
-    reinterpret_cast<T*>(smem + L.twt)[tid] = (T)v;
+    if (with_t) reinterpret_cast<T*>(smem + L.twt)[tid] = (T)v;
   }
 }
 
@@ -423,7 +459,9 @@ __global__ __launch_bounds__(64 * WAVES) void fse_dft64_kernel(BlockArgs<float> 
   const int wave = uniform_int(tid >> 6);
   const LdsLayout L = dft_layout(a.M, a.N, WAVES);
   const int item = blockIdx.x;
-  const int fr = a.items[2 * item], bij = a.items[2 * item + 1];
+  const int fw = a.items[2 * item], bij = a.items[2 * item + 1];
+  const int fr = fw & kItemFrameMask;
+  if (fw >> kItemPrioShift) __builtin_amdgcn_s_setprio(2);
   const int bi = bij >> 16, bj = bij & 0xffff;
   const FrameDesc fd = a.frames[fr];
   const int by0 = bi * a.Bh - a.goy, bx0 = bj * a.Bw - a.gox;
@@ -448,10 +486,12 @@ __global__ __launch_bounds__(64 * WAVES) void fse_dft64_kernel(BlockArgs<float> 
 }
 
 // RERANK (T = float only): spectra come from fse_dft64_kernel, and near-tied
-// selections are re-scored exactly in double.
+// selections are re-scored exactly in double. Its LDS (about 40 KB at K = 200)
+// lets four workgroups share a CU, so the register budget is set for 4 (with 4
+// wavefronts) or 8 (with 8 or 16) wavefronts per SIMD.
 template <typename T, int WAVES, bool RERANK>
-__global__ __launch_bounds__(64 * WAVES, (RERANK && WAVES == 4) ? 4 : 1) void fse_block_kernel(
-    BlockArgs<T> a) {
+__global__ __launch_bounds__(64 * WAVES, RERANK ? (WAVES == 4 ? 4 : 8) : 1) void
+fse_block_kernel(BlockArgs<T> a) {
   constexpr int THREADS = 64 * WAVES;
   constexpr int ROWS = kFft / WAVES;
   static_assert(!RERANK || sizeof(T) == 4, "re-rank mode iterates in float");
@@ -473,8 +513,12 @@ __global__ __launch_bounds__(64 * WAVES, (RERANK && WAVES == 4) ? 4 : 1) void fs
   Slot* slots = reinterpret_cast<Slot*>(smem + L.slots);
 
   const int item = blockIdx.x;
-  const int fr = a.items[2 * item];
+  const int fw = a.items[2 * item];
+  const int fr = fw & kItemFrameMask;
   const int bij = a.items[2 * item + 1];
+  // items on the critical chain of waves issue ahead of the other
+  // workgroups sharing their SIMDs
+  if (fw >> kItemPrioShift) __builtin_amdgcn_s_setprio(2);
   const int bi = bij >> 16, bj = bij & 0xffff;
   const FrameDesc fd = a.frames[fr];
   const int H = fd.H, W = fd.W;
@@ -482,7 +526,7 @@ __global__ __launch_bounds__(64 * WAVES, (RERANK && WAVES == 4) ? 4 : 1) void fs
   uint8_t* st = a.state + fd.off;
   const int by0 = bi * a.Bh - a.goy, bx0 = bj * a.Bw - a.gox;
 
-  load_twiddles<T>(smem, L, a.twid64);
+  load_twiddles<T>(smem, L, a.twid64, !RERANK);
 
   VecR<T, ROWS> rr, ri;
   T wvr[ROWS], wvi[ROWS];
@@ -605,16 +649,13 @@ __global__ __launch_bounds__(64 * WAVES, (RERANK && WAVES == 4) ? 4 : 1) void fs
           near = two ? 2 : 1;
         }
         FSlot* fs = reinterpret_cast<FSlot*>(smem + L.slots) + (it & 1) * WAVES;
-        int* nr = reinterpret_cast<int*>(smem + L.slots + 2 * WAVES * sizeof(FSlot)) +
-                  (it & 1) * WAVES;
         if (lane == 0) {
           FSlot v;
           v.key = wk;
-          v.k = (row_of<WAVES, SPLIT>(wave, jw) << 6) | lw;
+          v.k = (row_of<WAVES, SPLIT>(wave, jw) << 6) | lw | (near << 12);
           v.re = sr;
           v.im = si;
           fs[wave] = v;
-          if constexpr (RERANK) nr[wave] = near;
         }
         __syncthreads();
         // every lane reads the slot of wavefront lane % WAVES (one LDS round
@@ -623,13 +664,13 @@ __global__ __launch_bounds__(64 * WAVES, (RERANK && WAVES == 4) ? 4 : 1) void fs
         const FSlot mine = fs[lane & (WAVES - 1)];
         const unsigned gk = group_max<WAVES>(mine.key);
         const int wwin = uniform_int(wave_of_row<WAVES, SPLIT>(63 - (int)(gk & 63u)));
-        u = uniform_int(__builtin_amdgcn_readlane(mine.k, wwin));
+        u = uniform_int(__builtin_amdgcn_readlane(mine.k, wwin) & 0xfff);
         dcr = gs * read_lane(mine.re, wwin);
         dci = gs * read_lane(mine.im, wwin);
         if constexpr (RERANK) {
           const unsigned thr_g = __float_as_uint(__uint_as_float(gk) * (float)(1.0 - a.rerank_gap));
           const int contrib =
-              (lane < WAVES && mine.key >= thr_g) ? nr[lane & (WAVES - 1)] : 0;
+              (lane < WAVES && mine.key >= thr_g) ? (mine.k >> 12) : 0;
           const bool rerank = __ballot(contrib >= 2) != 0ull ||
                               __builtin_popcountll(__ballot(contrib >= 1)) >= 2;
           if (rerank) {  // uniform: every wavefront read the same slots
@@ -650,68 +691,68 @@ __global__ __launch_bounds__(64 * WAVES, (RERANK && WAVES == 4) ? 4 : 1) void fs
                 ++nc;
               }
             }
-            double accr[kCandWave], acci[kCandWave], r0r[kCandWave], r0i[kCandWave];
+            // exact |R|^2 of the wavefront's NC candidates (NC = nc, uniform):
+            // R0 - sum_i dc_i W[k - u_i] in double; the best one (ties to the
+            // smallest index) goes to (bex, bre, bim, bkx)
+            double bex = -1.0, bre = 0.0, bim = 0.0;
+            int bkx = 1 << 30;
+            auto rescore = [&](auto nc_tag) {
+              constexpr int NC = decltype(nc_tag)::value;
+              int kc[NC];
+              double acc[2 * NC], r0r[NC], r0i[NC];
 #pragma unroll
-            for (int c = 0; c < kCandWave; ++c) {
-              accr[c] = acci[c] = r0r[c] = r0i[c] = 0.0;
-              if (c < nc) {
-                const int kc = (int)((packed >> (12 * c)) & 0xfffull);
-                r0r[c] = spec[kSpecR0 + 2 * kc];
-                r0i[c] = spec[kSpecR0 + 2 * kc + 1];
+              for (int c = 0; c < NC; ++c) {
+                kc[c] = (int)((packed >> (12 * c)) & 0xfffull);
+                acc[2 * c] = acc[2 * c + 1] = 0.0;
+                r0r[c] = spec[kSpecR0 + 2 * kc[c]];
+                r0i[c] = spec[kSpecR0 + 2 * kc[c] + 1];
               }
-            }
-            // history terms in rounds of kRound x 64 so that all gathers of a
-            // round are in flight together (one memory latency per round)
-            constexpr int kRound = 2;
-            for (int i0 = 0; i0 < it; i0 += 64 * kRound) {
-              double wr[kRound][kCandWave], wi[kRound][kCandWave];
-              int valid[kRound];
+              // history terms in rounds of kRound x 64 so that all gathers of
+              // a round are in flight together (one memory latency per round)
+              constexpr int kRound = WAVES == 4 ? 2 : 1;  // register budget
+              for (int i0 = 0; i0 < it; i0 += 64 * kRound) {
+                double wr[kRound][NC], wi[kRound][NC];
 #pragma unroll
-              for (int q = 0; q < kRound; ++q) {
-                const int i = i0 + 64 * q + lane;
-                valid[q] = i < it;
-                const int uu = valid[q] ? hu[i] : 0;
+                for (int q = 0; q < kRound; ++q) {
+                  const int i = i0 + 64 * q + lane;
+                  const int uu = i < it ? hu[i] : 0;
 #pragma unroll
-                for (int c = 0; c < kCandWave; ++c) {
-                  wr[q][c] = wi[q][c] = 0.0;
-                  if (c < nc && valid[q]) {
-                    const int kc = (int)((packed >> (12 * c)) & 0xfffull);
-                    const int d1 = ((kc >> 6) - (uu >> 6)) & (kFft - 1);
-                    const int d2 = ((kc & (kFft - 1)) - (uu & (kFft - 1))) & (kFft - 1);
+                  for (int c = 0; c < NC; ++c) {
+                    const int d1 = ((kc[c] >> 6) - (uu >> 6)) & (kFft - 1);
+                    const int d2 = ((kc[c] & (kFft - 1)) - (uu & (kFft - 1))) & (kFft - 1);
                     wr[q][c] = spec[kSpecW + 2 * (d1 * kFft + d2)];
                     wi[q][c] = spec[kSpecW + 2 * (d1 * kFft + d2) + 1];
                   }
                 }
-              }
 #pragma unroll
-              for (int q = 0; q < kRound; ++q) {
-                const int i = i0 + 64 * q + lane;
-                const double xr = valid[q] ? (double)hdc[2 * i] : 0.0;
-                const double xi = valid[q] ? (double)hdc[2 * i + 1] : 0.0;
+                for (int q = 0; q < kRound; ++q) {
+                  const int i = i0 + 64 * q + lane;
+                  const double xr = i < it ? (double)hdc[2 * i] : 0.0;
+                  const double xi = i < it ? (double)hdc[2 * i + 1] : 0.0;
 #pragma unroll
-                for (int c = 0; c < kCandWave; ++c) {
-                  accr[c] = fma(xr, wr[q][c], fma(-xi, wi[q][c], accr[c]));
-                  acci[c] = fma(xr, wi[q][c], fma(xi, wr[q][c], acci[c]));
+                  for (int c = 0; c < NC; ++c) {
+                    acc[2 * c] = fma(xr, wr[q][c], fma(-xi, wi[q][c], acc[2 * c]));
+                    acc[2 * c + 1] = fma(xr, wi[q][c], fma(xi, wr[q][c], acc[2 * c + 1]));
+                  }
                 }
               }
-            }
-            double bex = -1.0, bre = 0.0, bim = 0.0;
-            int bkx = 1 << 30;
+              wave_sums(acc);
 #pragma unroll
-            for (int c = 0; c < kCandWave; ++c) {
-              if (c < nc) {
-                const int kc = (int)((packed >> (12 * c)) & 0xfffull);
-                const double vr = r0r[c] - wave_sum(accr[c]);
-                const double vi = r0i[c] - wave_sum(acci[c]);
+              for (int c = 0; c < NC; ++c) {
+                const double vr = r0r[c] - acc[2 * c];
+                const double vi = r0i[c] - acc[2 * c + 1];
                 const double ve = vr * vr + vi * vi;
-                if (ve > bex || (ve == bex && kc < bkx)) {
+                if (ve > bex || (ve == bex && kc[c] < bkx)) {
                   bex = ve;
                   bre = vr;
                   bim = vi;
-                  bkx = kc;
+                  bkx = kc[c];
                 }
               }
-            }
+            };
+            if (nc == 1) rescore(std::integral_constant<int, 1>());
+            else if (nc == 2) rescore(std::integral_constant<int, 2>());
+            else if (nc == 3) rescore(std::integral_constant<int, 3>());
             Slot* ex = reinterpret_cast<Slot*>(smem + L.cand) + (it & 1) * WAVES;
             if (lane == 0) {
               Slot v;
@@ -835,7 +876,7 @@ __global__ void fse_scatter_kernel(T* work, uint8_t* state, const FrameDesc* fra
                                    const int32_t* items, const T* staging, int Bh, int Bw,
                                    int gox, int goy) {
   const int item = blockIdx.x;
-  const int fr = items[2 * item], bij = items[2 * item + 1];
+  const int fr = items[2 * item] & kItemFrameMask, bij = items[2 * item + 1];
   const int bi = bij >> 16, bj = bij & 0xffff;
   const FrameDesc fd = frames[fr];
   const int nb = Bh * Bw;

@@ -383,20 +383,39 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
   // Frames are split into up to `groups` groups (largest first onto the
   // group with the fewest lost blocks); each group runs its own sequence of
   // steps on its own stream, so one group's small launches overlap another's.
-  // Inside a group frames start at staggered steps: step s of the group holds
-  // wave s - off[f] of its frame f.
+  // The deepest frames (crit_depth) take group 0 to themselves: their chain of
+  // waves is the batch's critical path.  Inside a group frames start at
+  // staggered steps: step s of the group holds wave s - off[f] of its frame f.
   const bool staged_mode = p.border_d > std::min(Bh, Bw);
   const int G = staged_mode ? 1 : std::max(1, std::min(pl->group_count(), n));
   std::vector<std::vector<int>> gframes(G);
+  bool crit_group = false;  // group 0 holds the deepest frames
   {
-    std::vector<int> byload(n);
-    for (int f = 0; f < n; ++f) byload[f] = f;
+    std::vector<int> byload;
+    if (G >= 2 && pl->crit_depth() > 0.0) {
+      int D = 0;
+      for (int f = 0; f < n; ++f) D = std::max(D, nwaves[f]);
+      for (int f = 0; f < n; ++f) {
+        if (nwaves[f] > 0 && nwaves[f] >= pl->crit_depth() * D)
+          gframes[0].push_back(f);
+        else
+          byload.push_back(f);
+      }
+      crit_group = !gframes[0].empty() && !byload.empty();
+      if (!crit_group) {
+        gframes[0].clear();
+        byload.clear();
+      }
+    }
+    const int g0 = crit_group ? 1 : 0;
+    if (!crit_group)
+      for (int f = 0; f < n; ++f) byload.push_back(f);
     std::stable_sort(byload.begin(), byload.end(),
                      [&](int x, int y) { return seq[x].size() > seq[y].size(); });
-    std::vector<int64_t> load(G, 0);
+    std::vector<int64_t> load(G - g0, 0);
     for (int f : byload) {
       const int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-      gframes[g].push_back(f);
+      gframes[g0 + g].push_back(f);
       load[g] += (int64_t)seq[f].size();
     }
     for (auto& v : gframes) std::sort(v.begin(), v.end());
@@ -427,6 +446,7 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
     }
     gstart[g].assign(steps + 1, 0);
     std::vector<size_t> pos(m, 0);
+    const int32_t prio = (crit_group && g == 0 && pl->crit_prio) ? 1 << kItemPrioShift : 0;
     for (int step = 0; step < steps; ++step) {
       gstart[g][step] = (int64_t)items.size() / 2;
       for (int k = 0; k < m; ++k) {
@@ -434,7 +454,7 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
         const int t = step - off[k];
         while (t >= 0 && pos[k] < seq[f].size() && wave_of[f][seq[f][pos[k]]] == t) {
           const int32_t b = seq[f][pos[k]++];
-          items.push_back(f);
+          items.push_back(f | prio);
           items.push_back(((b / wb[f]) << 16) | (b % wb[f]));
           item_src.emplace_back(f, b);
         }
@@ -530,7 +550,7 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
       a.trace_u = want_trace ? (int32_t*)pl->trace_u.ptr + i0 * K : nullptr;
       a.trace_dc = want_trace ? (T*)pl->trace_dc.ptr + i0 * K * 2 : nullptr;
       if (rerank) a.spec64 = (double*)pl->spec64.ptr + spec_base[g] * kSpecStride;
-      const int waves = pl->waves_for(step_total);
+      const int waves = pl->waves_for(crit_group && g == 0 ? cnt : step_total);
       if ((rc = chk(hipEventRecord(pl->events[3 * li], gs)))) return rc;
       if constexpr (std::is_same<T, float>::value) {
         if (rerank &&
@@ -703,6 +723,11 @@ int32_t fse_plan(const fse_params* p, void* hip_stream, fse_plan_t* out) {
     const int g = std::atoi(env);
     if (g >= 1 && g <= 16) pl->groups = g;
   }
+  if (const char* env = std::getenv("FSE_CRIT_DEPTH")) {
+    const double c = std::atof(env);
+    if (c >= 0.0 && c <= 1.0) pl->crit = c;
+  }
+  if (const char* env = std::getenv("FSE_CRIT_PRIO")) pl->crit_prio = std::atoi(env) != 0;
   if (const char* env = std::getenv("FSE_WAVE_THRESHOLDS")) {
     int t16 = 0, t8 = 0;
     if (std::sscanf(env, "%d,%d", &t16, &t8) == 2 && t16 >= 0 && t8 >= 0) {
@@ -754,7 +779,7 @@ int32_t fse_plan_destroy(fse_plan_t pl) {
 }
 
 int32_t fse_conceal_image(fse_plan_t pl, const fse_frame* frames, int32_t n) {
-  if (!pl || !frames || n < 1) return FSE_ERR_INVALID;
+  if (!pl || !frames || n < 1 || n > kItemFrameMask) return FSE_ERR_INVALID;
   const bool dev = (pl->p.flags & FSE_FLAG_DEVICE_PTRS) != 0;
   for (int f = 0; f < n; ++f) {
     int rc = validate_frame(&frames[f], dev);

@@ -429,8 +429,9 @@ def test_host_strides_and_aliased_output(precision):
 @pytest.mark.parametrize("precision", [fse.FSE_FP64, fse.FSE_FP32_RERANK, fse.FSE_FP32])
 def test_frame_groups_equal_one_group(monkeypatch, precision):
     """A batch split into frame groups on separate streams gives bit for bit
-    the results of one group (each frame keeps its wave order; the workgroup
-    shape is pinned so that both runs use the same kernels)."""
+    the results of one group, also with the deepest frames in a group of their
+    own (each frame keeps its wave order; the workgroup shape is pinned so
+    that all runs use the same kernels)."""
     monkeypatch.setenv("FSE_WAVE_THRESHOLDS", "0,0")
     rng = np.random.default_rng(41)
     frames = []
@@ -440,15 +441,19 @@ def test_frame_groups_equal_one_group(monkeypatch, precision):
     imgs, losts = [f[0] for f in frames], [f[1] for f in frames]
     p = fse.Params(border_d=14, iterations=60, precision=precision)
     res = {}
-    for groups in ("1", "4"):
+    # "4c": the deepest frames in a group of their own with raised wave
+    # priority (the schedules here have 2 to 16 waves; 3 frames reach 8)
+    for key, groups, crit in (("1", "1", "0"), ("4", "4", "0"), ("4c", "4", "0.5")):
         monkeypatch.setenv("FSE_FRAME_GROUPS", groups)
+        monkeypatch.setenv("FSE_CRIT_DEPTH", crit)
         with fse.Plan(p) as plan:
-            res[groups] = plan.fse_conceal_image(imgs, losts, want_float=True, trace=True)
+            res[key] = plan.fse_conceal_image(imgs, losts, want_float=True, trace=True)
             assert plan.last_call_stats()["groups"] == int(groups)
-    for a, b in zip(res["1"], res["4"]):
-        np.testing.assert_array_equal(a.out_f, b.out_f)
-        np.testing.assert_array_equal(a.out, b.out)
-        np.testing.assert_array_equal(a.trace_u, b.trace_u)
+    for key in ("4", "4c"):
+        for a, b in zip(res["1"], res[key]):
+            np.testing.assert_array_equal(a.out_f, b.out_f)
+            np.testing.assert_array_equal(a.out, b.out)
+            np.testing.assert_array_equal(a.trace_u, b.trace_u)
 
 
 # ------------------------------------------------------------ single launch
