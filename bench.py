@@ -280,7 +280,7 @@ def main():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-order", action="store_true")
     ap.add_argument("--no-e2e", action="store_true")
-    ap.add_argument("--precision", choices=("fp32", "fp32_rerank"), default="fp32_rerank",
+    ap.add_argument("--precision", choices=("fp32", "fp32_rerank", "fp32_f16x3"), default="fp32_rerank",
                     help="arithmetic of the headline batched run")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -344,15 +344,17 @@ def main():
                 "blocks_per_step": blocks // steps, "avg_launch_ms": kms / max(1, launches),
                 "blocks_per_launch": blocks / max(1, launches)}
 
-    names = {fse.FSE_FP32: "fp32", fse.FSE_FP32_RERANK: "fp32_rerank", fse.FSE_FP64: "fp64"}
-    head_prec = {"fp32": fse.FSE_FP32, "fp32_rerank": fse.FSE_FP32_RERANK}[args.precision]
+    names = {fse.FSE_FP32: "fp32", fse.FSE_FP32_RERANK: "fp32_rerank", fse.FSE_FP64: "fp64",
+             fse.FSE_FP32_F16X3: "fp32_f16x3"}
+    head_prec = {"fp32": fse.FSE_FP32, "fp32_rerank": fse.FSE_FP32_RERANK,
+                 "fp32_f16x3": fse.FSE_FP32_F16X3}[args.precision]
     log(f"[bench] batched {args.precision}: {args.steps} timed steps")
     head = batched(head_prec, args.steps, args.warmup)
     log(f"[bench] batched {args.precision}: {head['value']:.0f} blocks/s, "
         f"{head['ms_per_step']:.1f} ms/step, kernel {head['kernel_ms_per_step']:.1f} ms/step")
     sweep = {names[head_prec]: head}
     if not args.no_sweep:
-        for prec in (fse.FSE_FP32, fse.FSE_FP32_RERANK, fse.FSE_FP64):
+        for prec in (fse.FSE_FP32, fse.FSE_FP32_RERANK, fse.FSE_FP64, fse.FSE_FP32_F16X3):
             if prec == head_prec:
                 continue
             r = batched(prec, 2, 1)
@@ -414,7 +416,7 @@ def main():
     if not args.no_order:
         log("[bench] order comparison (512x512, p = 0.25)")
         oframes = order_frames(synth)
-        order = {"gpu": order_comparison_gpu(fse, oframes, head_prec), "oracle": None}
+        order = {"gpu": order_comparison_gpu(fse, oframes, head_prec)}
         log(f"[bench] order comparison: gain {order['gpu']['gain_db']:.3f} dB (GPU)")
         log("[bench] order comparison with sub-blocks (isolated / consecutive / mixed)")
         order["subblocks"] = subblock_order_gpu(fse, synth, head_prec)
@@ -427,14 +429,15 @@ def main():
         log("[bench] CPU oracle baseline")
         cpu = cpu_baseline(frames)
         if order is not None:
-            # the oracle's line scan is sequential: one 256x256 frame, with the
-            # GPU result on the same frame beside it
+            # part of the CPU baseline leg: the oracle's order comparison (its
+            # line scan is sequential, so one 256x256 frame), with the GPU
+            # result on the same frame under order["gpu_256"]
             small = [synth.config2(seed=0, size=256)]
-            order["oracle"] = {"frames": "one 256x256 frame (seed 0), p = 0.25",
-                               "oracle": order_comparison_oracle(small),
-                               "gpu": order_comparison_gpu(fse, small, head_prec, reps=1)}
-            log(f"[bench] order comparison: gain {order['oracle']['oracle']['gain_db']:.3f} dB "
-                f"(oracle), {order['oracle']['gpu']['gain_db']:.3f} dB (GPU), 256x256")
+            cpu["order_comparison_256"] = {"frames": "one 256x256 frame (seed 0), p = 0.25",
+                                           **order_comparison_oracle(small)}
+            order["gpu_256"] = order_comparison_gpu(fse, small, head_prec, reps=1)
+            log(f"[bench] order comparison: gain {cpu['order_comparison_256']['gain_db']:.3f} dB "
+                f"(oracle), {order['gpu_256']['gain_db']:.3f} dB (GPU), 256x256")
 
     line = {
         "metric": "lost blocks extrapolated/s (K=200) + p99 frame latency, FP32 batched vs FP64 plain",

@@ -61,10 +61,14 @@ enum { FSE_ORDER_OPTIMIZED = 0, FSE_ORDER_LINESCAN = 1 };
 enum {
   FSE_FP64 = 0,        /* spectra, weights, coefficients in double */
   FSE_FP32 = 1,        /* spectra and iteration in float; synthesis sums in double */
-  FSE_FP32_RERANK = 2  /* transforms in double, iteration in float; whenever another
+  FSE_FP32_RERANK = 2, /* transforms in double, iteration in float; whenever another
                           spectrum entry comes within rerank_gap (relative) of the
                           selected maximum of |R|^2, the candidates are re-scored
                           exactly in double (R0 - sum dc_i W[k - u_i]) */
+  FSE_FP32_F16X3 = 3    /* iteration as FSE_FP32; both DFT stages as dense products
+                          on matrix cores, every operand split into two f16 parts
+                          (about 22 significant bits; three products each, float
+                          accumulation); 4 wavefronts per block in every launch */
 };
 
 /* fse_params.flags */
@@ -79,7 +83,7 @@ typedef struct {
   double gamma;             /* orthogonality deficiency compensation, (0, 1] */
   int32_t iterations;       /* K, 1..FSE_MAX_ITERATIONS */
   int32_t order;            /* FSE_ORDER_* */
-  int32_t precision;        /* FSE_FP64, FSE_FP32 or FSE_FP32_RERANK */
+  int32_t precision;        /* FSE_FP64, FSE_FP32, FSE_FP32_RERANK, FSE_FP32_F16X3 */
   int32_t grid_off_x;       /* block grid shift, 0 <= off < block size: */
   int32_t grid_off_y;       /*   block column j covers x in
                                [j*block_w - grid_off_x, +block_w) */

@@ -33,6 +33,7 @@ FSE_ORDER_LINESCAN = 1
 FSE_FP64 = 0
 FSE_FP32 = 1
 FSE_FP32_RERANK = 2
+FSE_FP32_F16X3 = 3
 FSE_FLAG_DEVICE_PTRS = 1
 
 EXPORTED = ("fse_plan", "fse_plan_destroy", "fse_conceal_image", "fse_submit",
@@ -210,7 +211,8 @@ class _HostFrame:
         H, W = self.image.shape
         self.out = np.zeros((H, W), np.uint8)
         self.of32 = (np.zeros((H, W), np.float32)
-                     if want_float and precision in (FSE_FP32, FSE_FP32_RERANK) else None)
+                     if want_float and precision in (FSE_FP32, FSE_FP32_RERANK, FSE_FP32_F16X3)
+                     else None)
         self.of64 = np.zeros((H, W), np.float64) if want_float and precision == FSE_FP64 else None
         self.stats = _Stats()
         self.trace = None

@@ -232,40 +232,24 @@ __device__ __forceinline__ int j_of_row(int row, int wave) {
     return row - ROWS * wave;
 }
 
-// Phases A-C: gather and weight the area, transform, unpack.  Computes in T,
-// reads the working image in TI.  Returns W0 = sum of weights; when W0 > 0,
-// rr/ri hold X[k] and wvr/wvi hold W[k] for k1 = row_of(wave, j), k2 = lane
-// (split rows with 4 wavefronts).  With 4 wavefronts (COMPACT) phase A stages
-// the samples as TI and one weight class per sample and phase B forms the
-// weights again from the radial table, which keeps the staging small enough
-// for several blocks per CU; otherwise phase A stages x and w themselves.
-// Ends with a barrier, after which the LDS region may be reused.
+// Phase A: gather, classify and weight the area (Eq. (2)) into LDS; returns
+// W0 = sum of weights (uniform).  With 4 wavefronts (COMPACT) the samples are
+// staged as TI with one weight class per sample (0 none, 1 known, 2
+// reconstructed) at pitch N | 1; otherwise x = f w and w themselves.
 template <typename T, typename TI, int WAVES>
-__device__ __forceinline__ T forward_transforms(unsigned char* smem, const LdsLayout& L, int M,
-                                                int N, const T* radial, T delta, T zscale,
-                                                const TI* img, const uint8_t* st, int H, int W,
-                                                int oy, int ox, int lane, int wave,
-                                                VecR<T, kFft / WAVES>& rr,
-                                                VecR<T, kFft / WAVES>& ri,
-                                                T (&wvr)[kFft / WAVES], T (&wvi)[kFft / WAVES]) {
+__device__ __forceinline__ T gather_area(unsigned char* smem, const LdsLayout& L, int M, int N,
+                                         const T* radial, T delta, const TI* img,
+                                         const uint8_t* st, int H, int W, int oy, int ox,
+                                         int lane, int wave) {
   constexpr int THREADS = 64 * WAVES;
-  constexpr int ROWS = kFft / WAVES;
-  constexpr int QB = (kHalf + WAVES - 1) / WAVES;  // row-DFT columns per wavefront
-  constexpr bool SPLIT = WAVES == 4;
   constexpr bool COMPACT = WAVES == 4;
   const int tid = threadIdx.x;
   const int NP = N | 1;
-  T* xs = reinterpret_cast<T*>(smem);                     // x and w (full staging)
+  T* xs = reinterpret_cast<T*>(smem);
   T* ws = xs + M * NP;
-  TI* fs = reinterpret_cast<TI*>(smem);                   // COMPACT: samples
-  uint8_t* cs = reinterpret_cast<uint8_t*>(smem + L.cs);  // COMPACT: 0 none, 1 known, 2 recon
-  T* bx = reinterpret_cast<T*>(smem + L.bx);
-  T* bw = reinterpret_cast<T*>(smem + L.bw);
-  T* Zl = reinterpret_cast<T*>(smem);  // 64 x 64 complex, after phase B
-  T* twt = reinterpret_cast<T*>(smem + L.twt);
+  TI* fs = reinterpret_cast<TI*>(smem);
+  uint8_t* cs = reinterpret_cast<uint8_t*>(smem + L.cs);
   Slot* slots = reinterpret_cast<Slot*>(smem + L.slots);
-
-  // ---- A: gather, classify, weight (Eq. (2)) ----
   T wsum = T(0);
   for (int i = tid; i < M * N; i += THREADS) {
     const int m = i / N, n = i - m * N;
@@ -296,6 +280,41 @@ __device__ __forceinline__ T forward_transforms(unsigned char* smem, const LdsLa
   T W0 = T(0);
 #pragma unroll
   for (int q = 0; q < WAVES; ++q) W0 += (T)slots[q].e;
+  return W0;
+}
+
+// Phases A-C: gather and weight the area, transform, unpack.  Computes in T,
+// reads the working image in TI.  Returns W0 = sum of weights; when W0 > 0,
+// rr/ri hold X[k] and wvr/wvi hold W[k] for k1 = row_of(wave, j), k2 = lane
+// (split rows with 4 wavefronts).  With 4 wavefronts (COMPACT) phase A stages
+// the samples as TI and one weight class per sample and phase B forms the
+// weights again from the radial table, which keeps the staging small enough
+// for several blocks per CU; otherwise phase A stages x and w themselves.
+// Ends with a barrier, after which the LDS region may be reused.
+template <typename T, typename TI, int WAVES>
+__device__ __forceinline__ T forward_transforms(unsigned char* smem, const LdsLayout& L, int M,
+                                                int N, const T* radial, T delta, T zscale,
+                                                const TI* img, const uint8_t* st, int H, int W,
+                                                int oy, int ox, int lane, int wave,
+                                                VecR<T, kFft / WAVES>& rr,
+                                                VecR<T, kFft / WAVES>& ri,
+                                                T (&wvr)[kFft / WAVES], T (&wvi)[kFft / WAVES]) {
+  constexpr int ROWS = kFft / WAVES;
+  constexpr int QB = (kHalf + WAVES - 1) / WAVES;  // row-DFT columns per wavefront
+  constexpr bool SPLIT = WAVES == 4;
+  constexpr bool COMPACT = WAVES == 4;
+  const int NP = N | 1;
+  T* xs = reinterpret_cast<T*>(smem);                     // x and w (full staging)
+  T* ws = xs + M * NP;
+  TI* fs = reinterpret_cast<TI*>(smem);                   // COMPACT: samples
+  uint8_t* cs = reinterpret_cast<uint8_t*>(smem + L.cs);  // COMPACT: 0 none, 1 known, 2 recon
+  T* bx = reinterpret_cast<T*>(smem + L.bx);
+  T* bw = reinterpret_cast<T*>(smem + L.bw);
+  T* Zl = reinterpret_cast<T*>(smem);  // 64 x 64 complex, after phase B
+  T* twt = reinterpret_cast<T*>(smem + L.twt);
+
+  const T W0 = gather_area<T, TI, WAVES>(smem, L, M, N, radial, delta, img, st, H, W, oy, ox,
+                                         lane, wave);
   if (!(W0 > T(0))) return W0;
 
   // ---- B: real row DFTs, columns k2 = wave + WAVES q, k2 <= 32 ----
@@ -435,6 +454,234 @@ __device__ __forceinline__ T forward_transforms(unsigned char* smem, const LdsLa
   return W0;
 }
 
+// ---- Matrix-core transforms (FSE_FP32_F16X3) ----
+// Both DFT stages as real products on 16 x 16 x 32 f16 matrix-core tiles with
+// float accumulation.  Every operand v is split as v ~ hi + lo with
+// hi = f16(v), lo = f16(v - hi) (about 22 significant bits), and a product of
+// two split operands takes the three tiles hi*hi, hi*lo, lo*hi.  The operands
+// stay inside the f16 range: area samples are 8-bit values times weights <= 1,
+// row sums over at most 64 samples stay below 2^15, twiddles are <= 1, and a
+// lo part that falls below the normal range keeps an absolute error of 2^-24.
+// (Two bf16 parts carry only ~16 bits: measured, that split flipped too many
+// near-tied selections.)  Tile layout (16x16x32): lane l holds row l % 16 of A
+// and column l % 16 of B at k = 8 (l / 16) .. + 7, and column l % 16 of D at
+// rows 4 (l / 16) .. + 3.
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+// element e of (hi, lo) = the split of v
+template <typename V>
+__device__ __forceinline__ void split_f16(float v, V& hi, V& lo, int e) {
+  const _Float16 h = (_Float16)v;
+  hi[e] = h;
+  lo[e] = (_Float16)(v - (float)h);
+}
+
+__device__ __forceinline__ f32x4 mfma_f16x3(f16x8 ah, f16x8 al, f16x8 bh, f16x8 bl, f32x4 d) {
+  d = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh, d, 0, 0, 0);
+  d = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl, d, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh, d, 0, 0, 0);
+}
+
+__device__ __forceinline__ f16x8 neg_f16x8(f16x8 v) {
+  return __builtin_bit_cast(f16x8, __builtin_bit_cast(u32x4, v) ^ 0x80008000u);
+}
+
+// The row-DFT result of z = x + j s w, transposed (k2-major, 64 x 64) in four
+// f16 planes (Re hi, Re lo, Im hi, Im lo); 8-element chunks of a row are
+// XOR-swizzled by k2 so that the column reads of 16 lanes spread over banks.
+__device__ __forceinline__ int yt_index(int plane, int k2, int m) {
+  return plane * kFft * kFft + k2 * kFft + ((((m >> 3) ^ k2) & 7) << 3) + (m & 7);
+}
+
+// Phases A-C with 4 wavefronts on matrix cores; same contract as
+// forward_transforms<float, TI, 4>.
+//  B': [x; w] (64 x N, rows m) times G (N x 64): columns c <= 32 hold
+//      cos(2 pi c n / 64), c > 32 hold sin(2 pi (c - 32) n / 64); wavefront w
+//      computes rows 16w.. for both x and w.  The real row DFTs are then
+//      Y[m][c] = Yc - j Ys, extended to all 64 k2 by conjugate symmetry and
+//      combined into Yz = Yx + j s Yw.
+//  C': [Zr | Zi] (64 x 128) = [C | S] (64 x 128) times
+//      [[Yzr, Yzi], [Yzi, -Yzr]] (128 x 128) with C, S = cos, sin of
+//      2 pi k1 m / 64; wavefront w computes rows k1 = 16w.. .
+//  Unpack X and W from Z as in the vector path.
+template <typename TI>
+__device__ __forceinline__ float forward_transforms_mx(unsigned char* smem, const LdsLayout& L,
+                                                      int M, int N, const float* radial,
+                                                      float delta, float zscale, const TI* img,
+                                                      const uint8_t* st, int H, int W, int oy,
+                                                      int ox, int lane, int wave,
+                                                      VecR<float, 16>& rr, VecR<float, 16>& ri,
+                                                      float (&wvr)[16], float (&wvi)[16]) {
+  constexpr int WAVES = 4;
+  constexpr int ROWS = kFft / WAVES;
+  const float W0 = gather_area<float, TI, WAVES>(smem, L, M, N, radial, delta, img, st, H, W, oy,
+                                                 ox, lane, wave);
+  if (!(W0 > 0.f)) return W0;
+  const int NP = N | 1;
+  const TI* fs = reinterpret_cast<const TI*>(smem);
+  const uint8_t* cs = reinterpret_cast<const uint8_t*>(smem + L.cs);
+  const float* twt = reinterpret_cast<const float*>(smem + L.twt);
+  _Float16* yt = reinterpret_cast<_Float16*>(smem);  // after B': the four Yz planes
+  float* Zl = reinterpret_cast<float*>(smem);    // after C': Z, 64 x 64 complex
+  const int cl = lane & 15;      // tile row of A / column of B and D
+  const int kq = 8 * (lane >> 4);  // first k of the lane's fragments
+  const int rq = 4 * (lane >> 4);  // first D row of the lane
+
+  // ---- B': row DFTs ----
+  f32x4 dx[4], dw[4];
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) dx[ct] = dw[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+  {
+    const int m = ROWS * wave + cl;
+    for (int k0 = 0; k0 < N; k0 += 32) {
+      f16x8 xh, xl, wh, wl;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int n = k0 + kq + e;
+        float xv = 0.f, wv = 0.f;
+        if (m < M && n < N) {
+          const uint8_t c = cs[m * NP + n];
+          const float r = radial[m * N + n];
+          wv = c == 1 ? r : (c == 2 ? r * delta : 0.f);
+          xv = (float)fs[m * NP + n] * wv;
+        }
+        split_f16(xv, xh, xl, e);
+        split_f16(wv, wh, wl, e);
+      }
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) {
+        const int c = 16 * ct + cl;
+        const int kk = c <= 32 ? c : c - 32;
+        const int part = c <= 32 ? 0 : 1;  // cos or sin
+        f16x8 gh, gl;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int t = (kk * (k0 + kq + e)) & (kFft - 1);
+          split_f16(twt[2 * t + part], gh, gl, e);
+        }
+        dx[ct] = mfma_f16x3(xh, xl, gh, gl, dx[ct]);
+        dw[ct] = mfma_f16x3(wh, wl, gh, gl, dw[ct]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  }
+  __syncthreads();  // the staging is dead; the Yz planes take its place
+  {
+    const int m0 = ROWS * wave + rq;
+    auto put = [&](int k2, const float (&re)[4], const float (&im)[4]) {
+      f16x4 rh, rl, ih, il;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        split_f16(re[r], rh, rl, r);
+        split_f16(im[r], ih, il, r);
+      }
+      *reinterpret_cast<f16x4*>(yt + yt_index(0, k2, m0)) = rh;
+      *reinterpret_cast<f16x4*>(yt + yt_index(1, k2, m0)) = rl;
+      *reinterpret_cast<f16x4*>(yt + yt_index(2, k2, m0)) = ih;
+      *reinterpret_cast<f16x4*>(yt + yt_index(3, k2, m0)) = il;
+    };
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      const int c = 16 * ct + cl;  // 0..31; its sine column is 32 + c
+      float re[4], im[4], re2[4], im2[4];
+      if (c == 0) {
+        // k2 = 0 and k2 = 32 (column 32 holds the cosine of k2 = 32)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          re[r] = dx[0][r];
+          im[r] = zscale * dw[0][r];
+          re2[r] = dx[2][r];
+          im2[r] = zscale * dw[2][r];
+        }
+        put(0, re, im);
+        put(32, re2, im2);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float xc = dx[ct][r], xs = dx[ct + 2][r];
+          const float wc = dw[ct][r], ws = dw[ct + 2][r];
+          re[r] = fmaf(zscale, ws, xc);
+          im[r] = fmaf(zscale, wc, -xs);
+          re2[r] = fmaf(-zscale, ws, xc);
+          im2[r] = fmaf(zscale, wc, xs);
+        }
+        put(c, re, im);
+        put(kFft - c, re2, im2);
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- C': column DFTs ----
+  f32x4 dz[8];
+#pragma unroll
+  for (int ct = 0; ct < 8; ++ct) dz[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+  {
+    // A fragments of the 4 k-steps (k = 0..63: cos, 64..127: sin)
+    const int k1 = ROWS * wave + cl;
+    f16x8 ah[4], al[4];
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int part = ks >> 1;
+      const int mb = (32 * ks + kq) & (kFft - 1);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int t = (k1 * (mb + e)) & (kFft - 1);
+        split_f16(twt[2 * t + part], ah[ks], al[ks], e);
+      }
+    }
+#pragma unroll
+    for (int ct = 0; ct < 8; ++ct) {
+      const int k2 = 16 * (ct & 3) + cl;
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const int part = ks >> 1;
+        const int mb = (32 * ks + kq) & (kFft - 1);
+        // columns of Zr take (Yzr; Yzi), columns of Zi take (Yzi; -Yzr)
+        const int plane = ((ct < 4) == (part == 0)) ? 0 : 2;
+        f16x8 bh = *reinterpret_cast<const f16x8*>(yt + yt_index(plane, k2, mb));
+        f16x8 bl = *reinterpret_cast<const f16x8*>(yt + yt_index(plane + 1, k2, mb));
+        if (ct >= 4 && part == 1) {
+          bh = neg_f16x8(bh);
+          bl = neg_f16x8(bl);
+        }
+        dz[ct] = mfma_f16x3(ah[ks], al[ks], bh, bl, dz[ct]);
+      }
+      __builtin_amdgcn_sched_barrier(0);  // one output tile's operands live at a time
+    }
+  }
+  __syncthreads();  // the Yz planes are dead; Z takes their place
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k1 = ROWS * wave + rq + r, k2 = 16 * ct + cl;
+      *reinterpret_cast<float2*>(Zl + (k1 * kFft + k2) * 2) = make_float2(dz[ct][r], dz[ct + 4][r]);
+    }
+  }
+  __syncthreads();
+  // unpack: X[k] = (Z[k] + conj Z[-k]) / 2, W[k] = (Z[k] - conj Z[-k]) / (2 j s)
+  {
+    const float h = 0.5f, hs = 0.5f / zscale;
+#pragma unroll
+    for (int j = 0; j < ROWS; ++j) {
+      const int k1 = row_of<WAVES, true>(wave, j);
+      const float2 z = *reinterpret_cast<const float2*>(Zl + (k1 * kFft + lane) * 2);
+      const float2 p = *reinterpret_cast<const float2*>(
+          Zl + ((((kFft - k1) & (kFft - 1)) * kFft) + ((kFft - lane) & (kFft - 1))) * 2);
+      rr[j] = h * (z.x + p.x);
+      ri[j] = h * (z.y - p.y);
+      wvr[j] = hs * (z.y + p.y);
+      wvi[j] = hs * (p.x - z.x);
+    }
+  }
+  __syncthreads();
+  return W0;
+}
+
 // Twiddle tables into LDS (double for the synthesis, T for the transforms).
 template <typename T>
 __device__ __forceinline__ void load_twiddles(unsigned char* smem, const LdsLayout& L,
@@ -488,13 +735,16 @@ __global__ __launch_bounds__(64 * WAVES) void fse_dft64_kernel(BlockArgs<float> 
 // RERANK (T = float only): spectra come from fse_dft64_kernel, and near-tied
 // selections are re-scored exactly in double. Its LDS (about 40 KB at K = 200)
 // lets four workgroups share a CU, so the register budget is set for 4 (with 4
-// wavefronts) or 8 (with 8 or 16) wavefronts per SIMD.
-template <typename T, int WAVES, bool RERANK>
-__global__ __launch_bounds__(64 * WAVES, RERANK ? (WAVES == 4 ? 4 : 8) : 1) void
+// wavefronts) or 8 (with 8 or 16) wavefronts per SIMD.  MX (T = float, 4
+// wavefronts, no re-rank): the transforms run on matrix cores in split f16.
+template <typename T, int WAVES, bool RERANK, bool MX = false>
+__global__ __launch_bounds__(64 * WAVES, RERANK ? (WAVES == 4 ? 4 : 8) : (MX ? 4 : 1)) void
 fse_block_kernel(BlockArgs<T> a) {
   constexpr int THREADS = 64 * WAVES;
   constexpr int ROWS = kFft / WAVES;
   static_assert(!RERANK || sizeof(T) == 4, "re-rank mode iterates in float");
+  static_assert(!MX || (sizeof(T) == 4 && WAVES == 4 && !RERANK),
+                "matrix-core transforms: float, 4 wavefronts");
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -548,6 +798,9 @@ fse_block_kernel(BlockArgs<T> a) {
       }
     }
     __syncthreads();  // twiddles visible
+  } else if constexpr (MX) {
+    W0 = forward_transforms_mx<T>(smem, L, a.M, a.N, a.radial, a.delta, a.zscale, img, st, H, W,
+                                  by0 - a.d, bx0 - a.d, lane, wave, rr, ri, wvr, wvi);
   } else {
     W0 = forward_transforms<T, T, WAVES>(smem, L, a.M, a.N, a.radial, a.delta, a.zscale, img, st,
                                          H, W, by0 - a.d, bx0 - a.d, lane, wave, rr, ri, wvr,
@@ -953,15 +1206,16 @@ static hipError_t launch_with_lds(K kernel, size_t& attr_bytes, int n_items, int
   return hipGetLastError();
 }
 
-template <typename T, int WAVES, bool RERANK>
+template <typename T, int WAVES, bool RERANK, bool MX = false>
 static hipError_t launch_block_w(const BlockArgs<T>& a, int n_items, hipStream_t s) {
   static size_t attr_bytes = 0;  // largest dynamic LDS size enabled so far
   const size_t lds = (size_t)lds_bytes<T>(a.M, a.N, a.K, WAVES, !RERANK);
-  return launch_with_lds(fse_block_kernel<T, WAVES, RERANK>, attr_bytes, n_items, 64 * WAVES,
+  return launch_with_lds(fse_block_kernel<T, WAVES, RERANK, MX>, attr_bytes, n_items, 64 * WAVES,
                          lds, s, a);
 }
 
-// mode: 0 = plain, 1 = FP32 iterations on FP64 spectra with re-ranking
+// mode: 0 = plain, 1 = FP32 iterations on FP64 spectra with re-ranking,
+// 2 = FP32 with matrix-core f16x3 transforms (4 wavefronts only)
 template <typename T>
 hipError_t launch_block(const BlockArgs<T>& a, int n_items, int waves, hipStream_t s,
                         int mode = 0);
@@ -983,6 +1237,10 @@ template <>
 hipError_t launch_block<float>(const BlockArgs<float>& a, int n_items, int waves, hipStream_t s,
                                int mode) {
   if (n_items <= 0) return hipSuccess;
+  if (mode == 2) {
+    if (waves != 4) return hipErrorInvalidValue;
+    return launch_block_w<float, 4, false, true>(a, n_items, s);
+  }
   if (mode == 1) {
     switch (waves) {
       case 4: return launch_block_w<float, 4, true>(a, n_items, s);

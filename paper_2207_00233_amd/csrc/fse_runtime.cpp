@@ -93,7 +93,8 @@ int validate_params(const fse_params* p) {
   if (!(p->gamma > 0.0 && p->gamma <= 1.0)) return FSE_ERR_INVALID;
   if (p->iterations < 1 || p->iterations > FSE_MAX_ITERATIONS) return FSE_ERR_INVALID;
   if (p->order != FSE_ORDER_OPTIMIZED && p->order != FSE_ORDER_LINESCAN) return FSE_ERR_INVALID;
-  if (p->precision != FSE_FP64 && p->precision != FSE_FP32 && p->precision != FSE_FP32_RERANK)
+  if (p->precision != FSE_FP64 && p->precision != FSE_FP32 && p->precision != FSE_FP32_RERANK &&
+      p->precision != FSE_FP32_F16X3)
     return FSE_ERR_INVALID;
   if (!(p->rerank_gap >= 0.0 && p->rerank_gap < 0.5)) return FSE_ERR_INVALID;
   if (p->grid_off_x < 0 || p->grid_off_x >= p->block_w || p->grid_off_y < 0 ||
@@ -506,6 +507,7 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
   a.empty_fill = p.empty_fill;
   a.rerank_gap = p.rerank_gap > 0.0 ? p.rerank_gap : 1e-4;
   const bool rerank = p.precision == FSE_FP32_RERANK;
+  const bool mx = p.precision == FSE_FP32_F16X3;  // matrix-core transforms, 4 wavefronts
   // FP64 spectra: one slot per item of a step, per group (groups run at once)
   std::vector<int64_t> spec_base(G + 1, 0);
   for (int g = 0; g < G; ++g) {
@@ -550,7 +552,7 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
       a.trace_u = want_trace ? (int32_t*)pl->trace_u.ptr + i0 * K : nullptr;
       a.trace_dc = want_trace ? (T*)pl->trace_dc.ptr + i0 * K * 2 : nullptr;
       if (rerank) a.spec64 = (double*)pl->spec64.ptr + spec_base[g] * kSpecStride;
-      const int waves = pl->waves_for(crit_group && g == 0 ? cnt : step_total);
+      const int waves = mx ? 4 : pl->waves_for(crit_group && g == 0 ? cnt : step_total);
       if ((rc = chk(hipEventRecord(pl->events[3 * li], gs)))) return rc;
       if constexpr (std::is_same<T, float>::value) {
         if (rerank &&
@@ -558,7 +560,8 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
           return rc;
       }
       if ((rc = chk(hipEventRecord(pl->events[3 * li + 1], gs)))) return rc;
-      if ((rc = chk(launch_block<T>(a, (int)cnt, waves, gs, rerank ? 1 : 0)))) return rc;
+      if ((rc = chk(launch_block<T>(a, (int)cnt, waves, gs, rerank ? 1 : (mx ? 2 : 0)))))
+        return rc;
       if ((rc = chk(hipEventRecord(pl->events[3 * li + 2], gs)))) return rc;
       if (staged && (rc = chk(launch_scatter<T>(work, state, a.frames, a.items, (int)cnt,
                                                 (const T*)pl->staging.ptr, Bh, Bw, gox, goy, gs))))

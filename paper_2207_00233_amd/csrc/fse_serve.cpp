@@ -336,6 +336,7 @@ static void worker_loop(Serving* sv) {
   a.spec64 = nullptr;
   a.rerank_gap = p.rerank_gap > 0.0 ? p.rerank_gap : 1e-4;
   const bool rerank = p.precision == FSE_FP32_RERANK;
+  const bool mx = p.precision == FSE_FP32_F16X3;  // matrix-core transforms, 4 wavefronts
 
   auto fail_all = [&](int err) {
     std::lock_guard<std::mutex> lk(sv->mu);
@@ -414,7 +415,7 @@ static void worker_loop(Serving* sv) {
       }
       a.items = (const int32_t*)stp.items.ptr;
       a.staging = staged ? (T*)sv->d_staging.ptr : nullptr;
-      const int waves = pl->waves_for(n_items);
+      const int waves = mx ? 4 : pl->waves_for(n_items);
       if (hipMemcpyAsync(stp.items.ptr, stp.host.ptr, n_items * 2 * sizeof(int32_t),
                          hipMemcpyHostToDevice, s) != hipSuccess)
         return fail_all(FSE_ERR_DEVICE);
@@ -423,7 +424,7 @@ static void worker_loop(Serving* sv) {
                           hipSuccess)
           return fail_all(FSE_ERR_DEVICE);
       }
-      if (launch_block<T>(a, (int)n_items, waves, s, rerank ? 1 : 0) != hipSuccess)
+      if (launch_block<T>(a, (int)n_items, waves, s, rerank ? 1 : (mx ? 2 : 0)) != hipSuccess)
         return fail_all(FSE_ERR_DEVICE);
       if (staged && launch_scatter<T>(a.work, a.state, a.frames, a.items, (int)n_items, a.staging,
                                       p.block_h, p.block_w, p.grid_off_x, p.grid_off_y,

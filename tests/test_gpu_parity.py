@@ -21,7 +21,7 @@ import pytest
 import oracle
 import paper_2207_00233_amd as fse
 from paper_2207_00233_amd import synth
-from parity import index_agreement, psnr, teacher_forced_block
+from parity import index_agreement, mirror, psnr, teacher_forced_block
 
 pytestmark = pytest.mark.gpu
 
@@ -140,6 +140,69 @@ def test_fp64_trace_matches_oracle_trace():
         assert r.trace_wave[slot] == o.wave_of[b // wb, b % wb]
         agree, first_bad = index_agreement(o.u[b // wb, b % wb], r.trace_u[slot])
         assert agree == 1.0, (b, agree, first_bad)
+
+
+# ------------------------------------------------------------ f16x3 transforms
+# FSE_FP32_F16X3 computes both DFT stages on matrix cores with every operand
+# split into two f16 parts (about 22 significant bits, three products each,
+# float accumulation).  The bar: the first coefficient increment
+# gamma X[u] / W0 of every block within 1e-5 relative of the oracle's on the
+# same area (three split products lose ~2^-21 per term, float accumulation
+# ~1e-7 more), then the FP32 statistical bar per block (teacher-forced) and the
+# PSNR gap on whole images.
+
+F16X3_DC_TOL = 1e-5
+
+
+def test_f16x3_first_increment_matches_oracle():
+    fr = synth.config2(seed=6, size=96)
+    p = fse.Params(border_d=14, iterations=1, precision=fse.FSE_FP32_F16X3)
+    r = run_gpu(p, [fr.image], [fr.lost], trace=True)[0]
+    op = oracle_params(p)
+    grid = fr.lost.reshape(6, 16, 6, 16).any(axis=(1, 3)).astype(np.uint8)
+    _, wave_of, _ = oracle.schedule(grid)
+    worst = 0.0
+    for slot, b in enumerate(r.trace_block):
+        _, _, res = teacher_forced_block(fr.image, fr.lost, r.out_f.astype(np.float64),
+                                         wave_of, op, b // 6, b % 6)
+        u_o, dc_o = int(res.u[0]), complex(res.dc[0])
+        u_g, dc_g = int(r.trace_u[slot][0]), complex(r.trace_dc[slot][0])
+        if u_g != u_o:  # the exact mirror tie of a real area
+            assert u_g == int(mirror(u_o)), (b, u_g, u_o)
+            dc_o = dc_o.conjugate()
+        worst = max(worst, abs(dc_g - dc_o) / abs(dc_o))
+    print(f"[parity] f16x3 first increment: worst relative error {worst:.3e} over "
+          f"{len(r.trace_block)} blocks", flush=True)
+    assert worst <= F16X3_DC_TOL, worst
+
+
+@pytest.mark.parametrize("seed", [5, 11])
+def test_f16x3_teacher_forced_blocks(seed):
+    fr = synth.config2(seed=seed, size=128)
+    p = fse.Params(border_d=14, iterations=200, precision=fse.FSE_FP32_F16X3)
+    r = run_gpu(p, [fr.image], [fr.lost])[0]
+    op = oracle_params(p)
+    _, wave_of, seq = oracle.schedule(
+        fr.lost.reshape(8, 16, 8, 16).any(axis=(1, 3)).astype(np.uint8))
+    errs = np.array([np.abs(np.subtract(*teacher_forced_block(
+        fr.image, fr.lost, r.out_f.astype(np.float64), wave_of, op, b // 8, b % 8)[:2])).max()
+        for b in seq])
+    print(f"[parity] f16x3 teacher-forced median {np.median(errs):.3e} max {errs.max():.3e}, "
+          f"{np.mean(errs <= FP32_TOL):.3f} within {FP32_TOL} over {len(seq)} blocks", flush=True)
+    assert np.median(errs) <= 0.05
+    assert np.mean(errs <= FP32_TOL) >= 0.9
+
+
+def test_f16x3_free_running_and_batch_identity():
+    rng = np.random.default_rng(22)
+    img = synth.polygon_image(rng, 100, 120, radius=(10, 60))
+    lost = synth.bernoulli_block_loss(rng, 100, 120, 16, 0.35)
+    p = fse.Params(border_d=14, iterations=200, precision=fse.FSE_FP32_F16X3)
+    r, _ = check_free_running(p, img, lost, None, PSNR_GAP)
+    other = synth.polygon_image(rng, 64, 80, radius=(10, 30))
+    olost = synth.slice_loss(rng, 64, 80, 16, (0.2, 0.4))
+    rb = run_gpu(p, [other, img], [olost, lost])[1]
+    np.testing.assert_array_equal(rb.out_f, r.out_f)
 
 
 # ------------------------------------------------------------ edge cases
@@ -426,7 +489,8 @@ def test_host_strides_and_aliased_output(precision):
 
 # ------------------------------------------------------------ frame groups
 
-@pytest.mark.parametrize("precision", [fse.FSE_FP64, fse.FSE_FP32_RERANK, fse.FSE_FP32])
+@pytest.mark.parametrize("precision", [fse.FSE_FP64, fse.FSE_FP32_RERANK, fse.FSE_FP32,
+                                       fse.FSE_FP32_F16X3])
 def test_frame_groups_equal_one_group(monkeypatch, precision):
     """A batch split into frame groups on separate streams gives bit for bit
     the results of one group, also with the deepest frames in a group of their
