@@ -225,6 +225,36 @@ typedef struct {
 } fse_call_stats;
 int32_t fse_last_call_stats(fse_plan_t plan, fse_call_stats *out);
 
+/*
+ * Launch tuning of a plan: how batched calls and serving lay their work on
+ * the GPU (results stay within the per-shape rounding noted at fse_plan).
+ *   wave_threshold_16  launches of at most this many blocks run on 16
+ *                      wavefronts per block (default 256);
+ *   wave_threshold_8   larger launches of at most this many blocks run on 8
+ *                      (default 0: never); all others on 4;
+ *   frame_groups       frame groups of a batched call, 1..16; 0 = by
+ *                      precision (3 in FSE_FP32_RERANK, else 2);
+ *   crit_depth         frames with at least this fraction of the deepest
+ *                      frame's waves form group 0 (0 = off, at most 1); < 0 =
+ *                      by precision (0.9 in FSE_FP32_RERANK, else off);
+ *   crit_prio          1: group 0's workgroups raise their wave priority.
+ * FSE_FP32_F16X3 runs every launch on 4 wavefronts whatever the thresholds.
+ * fse_plan_get_tuning reports the values in effect (defaults resolved);
+ * fse_plan_set_tuning takes effect for launches issued after it returns
+ * (also those of frames already being served).  The environment variables
+ * of fse_plan set the same values at plan creation.
+ * Errors: FSE_ERR_INVALID (null pointer, value out of range).
+ */
+typedef struct {
+  int32_t wave_threshold_16;
+  int32_t wave_threshold_8;
+  int32_t frame_groups;
+  double crit_depth;
+  int32_t crit_prio;
+} fse_tuning;
+int32_t fse_plan_get_tuning(fse_plan_t plan, fse_tuning *out);
+int32_t fse_plan_set_tuning(fse_plan_t plan, const fse_tuning *t);
+
 /* Static description of an error code. */
 const char *fse_strerror(int32_t code);
 

@@ -37,7 +37,8 @@ FSE_FP32_F16X3 = 3
 FSE_FLAG_DEVICE_PTRS = 1
 
 EXPORTED = ("fse_plan", "fse_plan_destroy", "fse_conceal_image", "fse_submit",
-            "fse_poll", "fse_schedule", "fse_last_call_stats", "fse_strerror")
+            "fse_poll", "fse_schedule", "fse_last_call_stats", "fse_plan_get_tuning",
+            "fse_plan_set_tuning", "fse_strerror")
 
 
 class FseError(RuntimeError):
@@ -99,6 +100,15 @@ class _CallStats(ctypes.Structure):
                 ("groups", ctypes.c_int64), ("busy_ms", ctypes.c_double)]
 
 
+class _Tuning(ctypes.Structure):
+    _fields_ = [("wave_threshold_16", ctypes.c_int32), ("wave_threshold_8", ctypes.c_int32),
+                ("frame_groups", ctypes.c_int32), ("crit_depth", ctypes.c_double),
+                ("crit_prio", ctypes.c_int32)]
+
+
+TUNING_KEYS = ("wave_threshold_16", "wave_threshold_8", "frame_groups", "crit_depth", "crit_prio")
+
+
 @dataclasses.dataclass
 class Params:
     """Parameters of fse_plan (paper Section 4 defaults: d=16, rho=0.8,
@@ -154,6 +164,10 @@ def load():
     lib.fse_schedule.restype = ctypes.c_int32
     lib.fse_last_call_stats.argtypes = [ctypes.c_void_p, P(_CallStats)]
     lib.fse_last_call_stats.restype = ctypes.c_int32
+    lib.fse_plan_get_tuning.argtypes = [ctypes.c_void_p, P(_Tuning)]
+    lib.fse_plan_get_tuning.restype = ctypes.c_int32
+    lib.fse_plan_set_tuning.argtypes = [ctypes.c_void_p, P(_Tuning)]
+    lib.fse_plan_set_tuning.restype = ctypes.c_int32
     lib.fse_strerror.argtypes = [ctypes.c_int32]
     lib.fse_strerror.restype = ctypes.c_char_p
     _lib = lib
@@ -312,6 +326,24 @@ class Plan:
         return {"kernel_ms": cs.kernel_ms, "launches": cs.launches, "blocks": cs.blocks,
                 "total_ms": cs.total_ms, "transform_ms": cs.transform_ms,
                 "span_ms": cs.span_ms, "groups": cs.groups, "busy_ms": cs.busy_ms}
+
+    # -- fse_plan_get_tuning / fse_plan_set_tuning ------------------------------
+    def get_tuning(self) -> dict:
+        """Launch tuning in effect (defaults resolved)."""
+        t = _Tuning()
+        _check(self._lib.fse_plan_get_tuning(self.handle, ctypes.byref(t)), "fse_plan_get_tuning")
+        return {k: getattr(t, k) for k in TUNING_KEYS}
+
+    def set_tuning(self, **kw) -> None:
+        """Change some of the launch tuning (keys of TUNING_KEYS); the others
+        keep their values in effect."""
+        bad = set(kw) - set(TUNING_KEYS)
+        if bad:
+            raise KeyError(f"unknown tuning keys {sorted(bad)}")
+        cur = self.get_tuning()
+        cur.update(kw)
+        t = _Tuning(**cur)
+        _check(self._lib.fse_plan_set_tuning(self.handle, ctypes.byref(t)), "fse_plan_set_tuning")
 
     # -- fse_submit / fse_poll ------------------------------------------------
     def fse_submit(self, image: np.ndarray, lost: np.ndarray, want_float: bool = False,

@@ -77,19 +77,24 @@ struct fse_plan_s {
   // wavefronts per block by launch size: at most wide_threshold blocks -> 16,
   // at most mid_threshold -> 8, else 4 (fewer blocks than the GPU holds leave
   // SIMDs idle; more wavefronts per block shorten each block's iteration)
-  int wide_threshold = 256;
-  int mid_threshold = 0;
+  // (the tuning fields are atomic: fse_plan_set_tuning may change them while
+  // the serving worker issues launches)
+  std::atomic<int> wide_threshold{256};
+  std::atomic<int> mid_threshold{0};
   int waves_for(int64_t n_items) const {
-    return n_items <= wide_threshold ? 16 : (n_items <= mid_threshold ? 8 : 4);
+    return n_items <= wide_threshold.load(std::memory_order_relaxed)
+               ? 16
+               : (n_items <= mid_threshold.load(std::memory_order_relaxed) ? 8 : 4);
   }
   bool stagger = true;       // staggered frame starts inside a batch
   // frames of a batch run in up to `groups` groups on streams of their own
   // (0: by precision, measured on MI355X with the 64-frame batch: 3 groups
   // for the re-rank mode, whose two kernels per step overlap best, else 2;
   // more groups than hardware queues serialize)
-  int groups = 0;
+  std::atomic<int> groups{0};
   int group_count() const {
-    return groups > 0 ? groups : (p.precision == FSE_FP32_RERANK ? 3 : 2);
+    const int g = groups.load(std::memory_order_relaxed);
+    return g > 0 ? g : (p.precision == FSE_FP32_RERANK ? 3 : 2);
   }
   // frames whose schedule has at least crit_depth() x the waves of the
   // deepest frame of a batch form group 0 (when there are other frames): their
@@ -99,11 +104,12 @@ struct fse_plan_s {
   // wave priority (crit_prio).  0 = off; < 0 = by precision, measured on
   // MI355X with the 64-frame batch: 0.9 for the re-rank mode, whose per-step
   // transform pass lengthens the chain, else off
-  double crit = -1.0;
+  std::atomic<double> crit{-1.0};
   double crit_depth() const {
-    return crit >= 0.0 ? crit : (p.precision == FSE_FP32_RERANK ? 0.9 : 0.0);
+    const double c = crit.load(std::memory_order_relaxed);
+    return c >= 0.0 ? c : (p.precision == FSE_FP32_RERANK ? 0.9 : 0.0);
   }
-  bool crit_prio = true;
+  std::atomic<bool> crit_prio{true};
   std::vector<hipStream_t> gstreams;
   std::vector<hipEvent_t> gjoin;
   // launch cost model used to stagger frames: max(latency, blocks / rate),

@@ -810,6 +810,29 @@ int32_t fse_schedule(int32_t hb, int32_t wb, const uint8_t* lost, int32_t order,
   return nw;
 }
 
+int32_t fse_plan_get_tuning(fse_plan_t pl, fse_tuning* out) {
+  if (!pl || !out) return FSE_ERR_INVALID;
+  out->wave_threshold_16 = pl->wide_threshold.load();
+  out->wave_threshold_8 = pl->mid_threshold.load();
+  out->frame_groups = pl->group_count();
+  out->crit_depth = pl->crit_depth();
+  out->crit_prio = pl->crit_prio.load() ? 1 : 0;
+  return FSE_OK;
+}
+
+int32_t fse_plan_set_tuning(fse_plan_t pl, const fse_tuning* t) {
+  if (!pl || !t) return FSE_ERR_INVALID;
+  if (t->wave_threshold_16 < 0 || t->wave_threshold_8 < 0 || t->frame_groups < 0 ||
+      t->frame_groups > 16 || !(t->crit_depth <= 1.0) || (t->crit_prio != 0 && t->crit_prio != 1))
+    return FSE_ERR_INVALID;
+  pl->wide_threshold = t->wave_threshold_16;
+  pl->mid_threshold = t->wave_threshold_8;
+  pl->groups = t->frame_groups;
+  pl->crit = t->crit_depth < 0.0 ? -1.0 : t->crit_depth;
+  pl->crit_prio = t->crit_prio != 0;
+  return FSE_OK;
+}
+
 int32_t fse_last_call_stats(fse_plan_t pl, fse_call_stats* out) {
   if (!pl || !out) return FSE_ERR_INVALID;
   *out = pl->last;
