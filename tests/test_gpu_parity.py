@@ -392,6 +392,56 @@ def test_config3_full_batch_rerank_sampled_blocks():
     assert errs.max() <= FP32_TOL
 
 
+def _grid_of(lost, Bh=16, Bw=16):
+    H, W = lost.shape
+    hb, wb = -(-H // Bh), -(-W // Bw)
+    pad = np.zeros((hb * Bh, wb * Bw), bool)
+    pad[:H, :W] = lost.astype(bool)
+    return pad.reshape(hb, Bh, wb, Bw).any(axis=(1, 3)).astype(np.uint8)
+
+
+@pytest.mark.parametrize("precision,K,tol", [(fse.FSE_FP32_RERANK, 200, FP32_TOL),
+                                             (fse.FSE_FP64, 40, FP64_TOL)])
+def test_2160p_frame_sampled_blocks(precision, K, tol):
+    """The largest frame of the serving mix (3840 x 2160, slice losses): known
+    samples bit for bit, 12 seeded blocks fed to the oracle with the exact
+    area each saw."""
+    rng = np.random.default_rng(31)
+    img = synth.drifting_frame(np.random.default_rng(5), 2160, 3840, 0.0, rng)
+    lost = synth.slice_loss(rng, 2160, 3840, 16, (0.04, 0.08))
+    p = fse.Params(border_d=14, iterations=K, precision=precision)
+    r = run_gpu(p, [img], [lost])[0]
+    m = lost.astype(bool)
+    np.testing.assert_array_equal(r.out[~m], img[~m])
+    grid = _grid_of(lost)
+    wb = grid.shape[1]
+    _, wave_of, seq = oracle.schedule(grid)
+    op = oracle_params(p)
+    errs = []
+    for b in rng.choice(seq, 12, replace=False):
+        o_v, g_v, _ = teacher_forced_block(img, lost, r.out_f.astype(np.float64), wave_of, op,
+                                           b // wb, b % wb)
+        errs.append(np.abs(o_v - g_v).max())
+    print(f"[parity] 2160p prec {precision}: {len(seq)} lost blocks, {r.waves} waves, sampled "
+          f"max-abs {max(errs):.3e}", flush=True)
+    assert r.waves == int(wave_of.max()) + 1
+    assert max(errs) <= tol
+
+
+@pytest.mark.parametrize("Bh,Bw,d", [(8, 16, 6), (16, 8, 10), (12, 4, 10)])
+def test_rectangular_blocks_fp64(Bh, Bw, d):
+    """Blocks of unequal height and width (areas of (Bh + 2d) x (Bw + 2d)),
+    with d below and above the smaller block side."""
+    rng = np.random.default_rng(Bh * 100 + Bw)
+    img = synth.polygon_image(rng, 72, 88, radius=(8, 40))
+    lost = np.zeros_like(img)
+    grid = rng.random((-(-72 // Bh), -(-88 // Bw))) < 0.3
+    for i, j in zip(*np.nonzero(grid)):
+        lost[i * Bh:(i + 1) * Bh, j * Bw:(j + 1) * Bw] = 1
+    p = fse.Params(block_h=Bh, block_w=Bw, border_d=d, iterations=30, precision=fse.FSE_FP64)
+    check_free_running(p, img, lost, FP64_TOL)
+
+
 # ------------------------------------------------------------ launch shapes
 
 SHAPES = {"4 wavefronts": "0,0", "8 wavefronts": "0,1000000", "16 wavefronts": "1000000,0"}
