@@ -233,16 +233,15 @@ __device__ __forceinline__ int j_of_row(int row, int wave) {
 }
 
 // Phase A: gather, classify and weight the area (Eq. (2)) into LDS; returns
-// W0 = sum of weights (uniform).  With 4 wavefronts (COMPACT) the samples are
-// staged as TI with one weight class per sample (0 none, 1 known, 2
-// reconstructed) at pitch N | 1; otherwise x = f w and w themselves.
-template <typename T, typename TI, int WAVES>
+// W0 = sum of weights (uniform).  COMPACT: the samples are staged as TI with
+// one weight class per sample (0 none, 1 known, 2 reconstructed) at pitch
+// N | 1; otherwise x = f w and w themselves (T each, x first).
+template <typename T, typename TI, int WAVES, bool COMPACT = (WAVES == 4)>
 __device__ __forceinline__ T gather_area(unsigned char* smem, const LdsLayout& L, int M, int N,
                                          const T* radial, T delta, const TI* img,
                                          const uint8_t* st, int H, int W, int oy, int ox,
                                          int lane, int wave) {
   constexpr int THREADS = 64 * WAVES;
-  constexpr bool COMPACT = WAVES == 4;
   const int tid = threadIdx.x;
   const int NP = N | 1;
   T* xs = reinterpret_cast<T*>(smem);
@@ -323,17 +322,7 @@ __device__ __forceinline__ T forward_transforms(unsigned char* smem, const LdsLa
 #pragma unroll
     for (int q = 0; q < QB; ++q) axr[q] = axi[q] = awr[q] = awi[q] = T(0);
     if (lane < M) {
-      for (int n = 0; n < N; ++n) {
-        T xv, wv;
-        if constexpr (COMPACT) {
-          const uint8_t c = cs[lane * NP + n];
-          const T r = radial[lane * N + n];
-          wv = c == 1 ? r : (c == 2 ? r * delta : T(0));
-          xv = (T)fs[lane * NP + n] * wv;
-        } else {
-          xv = xs[lane * NP + n];
-          wv = ws[lane * NP + n];
-        }
+      auto accumulate = [&](int n, T xv, T wv) {
 #pragma unroll
         for (int q = 0; q < QB; ++q) {
           const int t = ((wave + WAVES * q) * n) & (kFft - 1);
@@ -342,6 +331,16 @@ __device__ __forceinline__ T forward_transforms(unsigned char* smem, const LdsLa
           axi[q] = fma(-xv, s, axi[q]);
           awr[q] = fma(wv, c, awr[q]);
           awi[q] = fma(-wv, s, awi[q]);
+        }
+      };
+      for (int n = 0; n < N; ++n) {
+        if constexpr (COMPACT) {
+          const uint8_t c = cs[lane * NP + n];
+          const T r = radial[lane * N + n];
+          const T wv = c == 1 ? r : (c == 2 ? r * delta : T(0));
+          accumulate(n, (T)fs[lane * NP + n] * wv, wv);
+        } else {
+          accumulate(n, xs[lane * NP + n], ws[lane * NP + n]);
         }
       }
 #pragma unroll
@@ -694,17 +693,32 @@ __device__ __forceinline__ void load_twiddles(unsigned char* smem, const LdsLayo
   }
 }
 
-// FP64 transform pass of the re-rank mode: writes R0, W and W0 of every work
-// item in double to BlockArgs::spec64 (the iteration kernel runs in float).
-template <int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void fse_dft64_kernel(BlockArgs<float> a,
-                                                               const double* radial64) {
-  constexpr int ROWS = kFft / WAVES;
+// FP64 transform pass of the re-rank mode: writes R0 = DFT(x), W = DFT(w)
+// and W0 of every work item in double to BlockArgs::spec64 (the iteration
+// kernel runs in float).  4 wavefronts.
+//  A: gather and weight the area: x = f w and w staged in double.
+//  B: real row DFTs of x and w (lane = row m, wavefront w takes the columns
+//     k2 = w + 4q <= 32), written over the dead staging.
+//  C: 64-point DFTs down 64 column sources at once, one per lane: lanes 0-31
+//     take x, lanes 32-63 take w; lane c >= 1 of a half takes column c, lane
+//     0 takes columns 0 and 32 packed as Y[m][0] + j Y[m][32] (both real for
+//     a real area).  The DFT is factorized 4 x 16 (wavefront w sums the rows
+//     m = w + 4 m1 for 16 outputs; the partial sums meet in LDS, one half of
+//     the outputs at a time, so the exchange needs 32 KB).  A column c >= 1
+//     gives X[k1][c] and, by conjugate symmetry, X[-k1][64 - c]; the packed
+//     column is unpacked with its mirrored rows.  No exchange buffer for the
+//     unpacking of a z = x + j s w transform: the outputs go to HBM, where
+//     the symmetry is applied on writing.  LDS ~49 KB at a 44 x 44 area
+//     (the staging, 31 KB, lies under the row DFTs), three workgroups per CU.
+__global__ __launch_bounds__(256, 3) void fse_dft64_kernel(BlockArgs<float> a,
+                                                           const double* radial64) {
+  constexpr int WAVES = 4, ROWS = kFft / WAVES, QB = (kHalf + WAVES - 1) / WAVES;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = uniform_int(tid >> 6);
-  const LdsLayout L = dft_layout(a.M, a.N, WAVES);
+  const int M = a.M, N = a.N, NP = N | 1;
+  const LdsLayout L = dft_layout(M, N, WAVES);
   const int item = blockIdx.x;
   const int fw = a.items[2 * item], bij = a.items[2 * item + 1];
   const int fr = fw & kItemFrameMask;
@@ -713,21 +727,136 @@ __global__ __launch_bounds__(64 * WAVES) void fse_dft64_kernel(BlockArgs<float> 
   const FrameDesc fd = a.frames[fr];
   const int by0 = bi * a.Bh - a.goy, bx0 = bj * a.Bw - a.gox;
   load_twiddles<double>(smem, L, a.twid64);
-  VecR<double, ROWS> rr, ri;
-  double wvr[ROWS], wvi[ROWS];
-  const double W0 = forward_transforms<double, float, WAVES>(
-      smem, L, a.M, a.N, radial64, a.delta64, 128.0, a.work + fd.off, a.state + fd.off,
-      fd.H, fd.W, by0 - a.d, bx0 - a.d, lane, wave, rr, ri, wvr, wvi);
+  const double W0 = gather_area<double, float, WAVES, false>(
+      smem, L, M, N, radial64, a.delta64, a.work + fd.off, a.state + fd.off, fd.H, fd.W,
+      by0 - a.d, bx0 - a.d, lane, wave);
   double* out = a.spec64 + (int64_t)item * kSpecStride;
   if (tid == 0) out[kSpecW0] = W0;
-  if (W0 > 0.0) {
+  if (!(W0 > 0.0)) return;  // uniform
+  const double* xs = reinterpret_cast<const double*>(smem);  // staged x = f w, then w
+  const double* ws = xs + M * NP;
+  const double* twt = reinterpret_cast<const double*>(smem + L.twt);
+  double* bx = reinterpret_cast<double*>(smem + L.bx);
+  double* bw = reinterpret_cast<double*>(smem + L.bw);
+  double* zx = reinterpret_cast<double*>(smem);                 // C exchange
+  double* pk = reinterpret_cast<double*>(smem + kDftExchange);  // packed columns
+
+  // ---- B: real row DFTs ----
+  {
+    double axr[QB], axi[QB], awr[QB], awi[QB];
+#pragma unroll
+    for (int q = 0; q < QB; ++q) axr[q] = axi[q] = awr[q] = awi[q] = 0.0;
+    if (lane < M) {
+      for (int n = 0; n < N; ++n) {
+        const double xv = xs[lane * NP + n], wv = ws[lane * NP + n];
+#pragma unroll
+        for (int q = 0; q < QB; ++q) {
+          const int t = ((wave + WAVES * q) * n) & (kFft - 1);
+          const double cc = twt[2 * t], ss = twt[2 * t + 1];
+          axr[q] = fma(xv, cc, axr[q]);
+          axi[q] = fma(-xv, ss, axi[q]);
+          awr[q] = fma(wv, cc, awr[q]);
+          awi[q] = fma(-wv, ss, awi[q]);
+        }
+      }
+    }
+    __syncthreads();  // the staging is dead
+    if (lane < M) {
+#pragma unroll
+      for (int q = 0; q < QB; ++q) {
+        const int k2 = wave + WAVES * q;
+        if (k2 < kHalf) {
+          bx[(lane * kHalf + k2) * 2] = axr[q];
+          bx[(lane * kHalf + k2) * 2 + 1] = axi[q];
+          bw[(lane * kHalf + k2) * 2] = awr[q];
+          bw[(lane * kHalf + k2) * 2 + 1] = awi[q];
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- C: column DFTs, lane = column source ----
+  const int part = lane >> 5, c = lane & 31;
+  const double* src = part ? bw : bx;
+  const int i_re = c == 0 ? 0 : 2 * c;               // Y[m][c].re, or Y[m][0].re
+  const int i_im = c == 0 ? 2 * (kFft / 2) : 2 * c + 1;  // Y[m][c].im, or Y[m][32].re
+  double pr[ROWS], pi[ROWS];  // partial 16-point DFTs of the rows m = wave + 4 m1
+#pragma unroll
+  for (int j = 0; j < ROWS; ++j) pr[j] = pi[j] = 0.0;
+  for (int m = wave; m < M; m += WAVES) {
+    const double zr = src[m * 2 * kHalf + i_re], zi = src[m * 2 * kHalf + i_im];
+    const int m1 = m >> 2;
 #pragma unroll
     for (int j = 0; j < ROWS; ++j) {
-      const int k = row_of<WAVES, WAVES == 4>(wave, j) * kFft + lane;
-      out[kSpecR0 + 2 * k] = rr[j];
-      out[kSpecR0 + 2 * k + 1] = ri[j];
-      out[kSpecW + 2 * k] = wvr[j];
-      out[kSpecW + 2 * k + 1] = wvi[j];
+      const int t = (4 * m1 * j) & (kFft - 1);
+      const double cc = twt[2 * t], ss = twt[2 * t + 1];
+      pr[j] = fma(zr, cc, fma(zi, ss, pr[j]));
+      pi[j] = fma(zi, cc, fma(-zr, ss, pi[j]));
+    }
+  }
+  // combine Z[k1] = sum_m0 e^{-j 2 pi m0 k1 / 64} P_m0[k1 mod 16]; the rows of
+  // wavefront w have k1 mod 16 in [8 (w & 1), 8 (w & 1) + 8)
+  double zr_[ROWS], zi_[ROWS];
+  __syncthreads();  // every wavefront is done reading the row DFTs
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if (h == 1) __syncthreads();  // half 0 consumed
+#pragma unroll
+    for (int jl = 0; jl < 8; ++jl) {
+      double* p = zx + ((wave * 8 + jl) * kFft + lane) * 2;
+      p[0] = pr[8 * h + jl];
+      p[1] = pi[8 * h + jl];
+    }
+    __syncthreads();
+    if ((wave & 1) == h) {
+#pragma unroll
+      for (int j = 0; j < ROWS; ++j) {
+        const int k1 = row_of<WAVES, true>(wave, j);
+        const int jl = (k1 & 15) - 8 * h;
+        double ar = 0.0, ai = 0.0;
+#pragma unroll
+        for (int m0 = 0; m0 < WAVES; ++m0) {
+          const double* p = zx + ((m0 * 8 + jl) * kFft + lane) * 2;
+          const double yr = p[0], yi = p[1];
+          const int t = (m0 * k1) & (kFft - 1);
+          const double cc = twt[2 * t], ss = twt[2 * t + 1];
+          ar = fma(yr, cc, fma(yi, ss, ar));
+          ai = fma(yi, cc, fma(-yr, ss, ai));
+        }
+        zr_[j] = ar;
+        zi_[j] = ai;
+      }
+    }
+  }
+  // packed columns: their outputs for every row, for the mirrored reads
+  if (c == 0) {
+#pragma unroll
+    for (int j = 0; j < ROWS; ++j) {
+      const int k1 = row_of<WAVES, true>(wave, j);
+      pk[(part * kFft + k1) * 2] = zr_[j];
+      pk[(part * kFft + k1) * 2 + 1] = zi_[j];
+    }
+  }
+  __syncthreads();
+  double* dst = out + (part ? kSpecW : kSpecR0);
+#pragma unroll
+  for (int j = 0; j < ROWS; ++j) {
+    const int k1 = row_of<WAVES, true>(wave, j);
+    const int km = (kFft - k1) & (kFft - 1);
+    if (c != 0) {
+      dst[2 * (k1 * kFft + c)] = zr_[j];
+      dst[2 * (k1 * kFft + c) + 1] = zi_[j];
+      dst[2 * (km * kFft + kFft - c)] = zr_[j];
+      dst[2 * (km * kFft + kFft - c) + 1] = -zi_[j];
+    } else {
+      // P = A + j B with A, B the DFTs of the real columns 0 and 32:
+      // A = (P[k] + conj P[-k]) / 2, B = (P[k] - conj P[-k]) / (2 j)
+      const double qr = pk[(part * kFft + km) * 2], qi = pk[(part * kFft + km) * 2 + 1];
+      dst[2 * (k1 * kFft)] = 0.5 * (zr_[j] + qr);
+      dst[2 * (k1 * kFft) + 1] = 0.5 * (zi_[j] - qi);
+      dst[2 * (k1 * kFft + kFft / 2)] = 0.5 * (zi_[j] + qi);
+      dst[2 * (k1 * kFft + kFft / 2) + 1] = 0.5 * (qr - zr_[j]);
     }
   }
 }
@@ -1264,7 +1393,7 @@ hipError_t launch_dft64(const BlockArgs<float>& a, const double* radial64, int n
   if (n_items <= 0) return hipSuccess;
   static size_t attr_bytes = 0;
   const size_t lds = (size_t)dft_layout(a.M, a.N, 4).total;
-  return launch_with_lds(fse_dft64_kernel<4>, attr_bytes, n_items, 256, lds, s, a, radial64);
+  return launch_with_lds(fse_dft64_kernel, attr_bytes, n_items, 256, lds, s, a, radial64);
 }
 
 template <typename T>
