@@ -18,6 +18,7 @@ import os
 import sys
 import time
 
+
 import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -283,9 +284,15 @@ def main():
     ap.add_argument("--precision", choices=("fp32", "fp32_rerank", "fp32_f16x3"), default="fp32_rerank",
                     help="arithmetic of the headline batched run")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--hw-queues", type=int, default=8, choices=range(1, 33), metavar="1..32",
+                    help="GPU_MAX_HW_QUEUES for this process (default 8)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 512 MiB device copy 3 times (HBM counter scale)")
     args = ap.parse_args()
+    # hardware queues per process (HIP's default is 4): with 8 the re-rank
+    # mode's frame groups take four streams besides the caller's; set before
+    # anything initializes HIP
+    os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(frames would shard across GPUs without communication)", file=sys.stderr)
@@ -459,7 +466,8 @@ def main():
                                + (" with FP64 transforms and near-tie re-ranking"
                                   if args.precision == "fp32_rerank" else ""),
                    "lost_blocks_per_step": lost_blocks, "frames": len(frames),
-                   "launches_per_step": launches // args.steps},
+                   "launches_per_step": launches // args.steps,
+                   "hip_hw_queues": int(os.environ["GPU_MAX_HW_QUEUES"])},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
                      "kernel": "fse_block_kernel<float>",

@@ -144,7 +144,8 @@ typedef struct {
  * or on 8 wavefronts instead of 4; results equal the oracle's to the same
  * tolerance in every shape, not bit for bit across shapes.
  * FSE_FRAME_GROUPS=g (1..16) sets the number of frame groups of a batched
- * call (default 3 in FSE_FP32_RERANK, else 2).  FSE_CRIT_DEPTH=c (0..1):
+ * call (default 3 in FSE_FP32_RERANK, 4 when the process runs with
+ * GPU_MAX_HW_QUEUES >= 8, else 2).  FSE_CRIT_DEPTH=c (0..1):
  * frames whose schedule has at least c times the waves of the deepest frame
  * form a group of their own with the launch shape of their own size and a
  * raised wave priority (FSE_CRIT_PRIO=0 keeps the default priority); 0 = off,
@@ -233,7 +234,8 @@ int32_t fse_last_call_stats(fse_plan_t plan, fse_call_stats *out);
  *   wave_threshold_8   larger launches of at most this many blocks run on 8
  *                      (default 0: never); all others on 4;
  *   frame_groups       frame groups of a batched call, 1..16; 0 = by
- *                      precision (3 in FSE_FP32_RERANK, else 2);
+ *                      precision (3 in FSE_FP32_RERANK, 4 with
+ *                      GPU_MAX_HW_QUEUES >= 8, else 2);
  *   crit_depth         frames with at least this fraction of the deepest
  *                      frame's waves form group 0 (0 = off, at most 1); < 0 =
  *                      by precision (0.9 in FSE_FP32_RERANK, else off);

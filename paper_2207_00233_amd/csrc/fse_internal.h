@@ -89,12 +89,16 @@ struct fse_plan_s {
   bool stagger = true;       // staggered frame starts inside a batch
   // frames of a batch run in up to `groups` groups on streams of their own
   // (0: by precision, measured on MI355X with the 64-frame batch: 3 groups
-  // for the re-rank mode, whose two kernels per step overlap best, else 2;
-  // more groups than hardware queues serialize)
+  // for the re-rank mode, whose two kernels per step overlap best (4 with 8
+  // hardware queues), else 2; more groups than hardware queues serialize)
   std::atomic<int> groups{0};
+  int hw_queues = 4;  // hardware queues of the process (GPU_MAX_HW_QUEUES, HIP's default 4)
   int group_count() const {
     const int g = groups.load(std::memory_order_relaxed);
-    return g > 0 ? g : (p.precision == FSE_FP32_RERANK ? 3 : 2);
+    if (g > 0) return g;
+    // re-rank: 3 groups fit the default 4 hardware queues (one holds the
+    // caller's stream); with 8 queues a fourth group overlaps as well
+    return p.precision == FSE_FP32_RERANK ? (hw_queues >= 8 ? 4 : 3) : 2;
   }
   // frames whose schedule has at least crit_depth() x the waves of the
   // deepest frame of a batch form group 0 (when there are other frames): their

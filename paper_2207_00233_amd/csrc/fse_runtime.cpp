@@ -722,6 +722,10 @@ int32_t fse_plan(const fse_params* p, void* hip_stream, fse_plan_t* out) {
     }
     pl->own_stream = true;
   }
+  if (const char* env = std::getenv("GPU_MAX_HW_QUEUES")) {
+    const int q = std::atoi(env);
+    if (q >= 1) pl->hw_queues = q;
+  }
   if (const char* env = std::getenv("FSE_FRAME_GROUPS")) {
     const int g = std::atoi(env);
     if (g >= 1 && g <= 16) pl->groups = g;
