@@ -16,12 +16,15 @@
 //      r -= dc * phi_u;
 //   E  the model of Eq. (1) evaluated on the lost samples of the block (sums
 //      in double), written back as reconstructed samples.
-// Spectrum layout in the iteration: wavefront w owns rows k1 = ROWS*w ..
-// ROWS*w + ROWS-1 (ROWS = 64 / WAVES), lane l owns column k2 = l, so every lane
-// keeps ROWS complex entries in registers and reads W[k - u] from LDS with a
-// per-lane column offset.  WAVES = 4 is the throughput shape; WAVES = 8 and 16
-// halve and quarter the serial work per iteration for launches too small to
-// fill the GPU.
+// Spectrum layout in the iteration: wavefront w owns ROWS = 64 / WAVES rows
+// k1 (rows ROWS*w .. ROWS*w + ROWS-1; with 4 wavefronts two windows of 8 rows,
+// 8w.. and 32 + 8w..), lane l owns column k2 = l, so every lane keeps ROWS
+// complex entries in registers and reads W[k - u] from LDS with a per-lane
+// column offset.  WAVES = 4 is the throughput shape; WAVES = 8 and 16 halve
+// and quarter the serial work per iteration for launches too small to fill
+// the GPU.  The FP64 transform pass of the re-rank mode (fse_dft64_kernel)
+// and the matrix-core transforms (forward_transforms_mx) replace phases A-C
+// and are described where they are defined.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -194,7 +197,8 @@ struct FSlot {
 
 // Argmax slot exchanged between wavefronts (32 bytes).
 struct Slot {
-  double e;     // FP64 path: exact |R|^2 of the wave's best entry; re-rank: near-tie count
+  double e;     // FP64 path: exact |R|^2 of the wave's best entry; re-rank: exact |R|^2 of
+                // the wave's best re-scored candidate
   double re, im;
   unsigned key; // FP32 path: packed selection key of the wave's best entry
   int k;        // its spectrum index k1 * 64 + k2
