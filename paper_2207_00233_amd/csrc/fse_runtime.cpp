@@ -234,6 +234,19 @@ static void parallel_for(fse_plan_s* pl, int n, const std::function<void(int)>& 
   pl->pool->run(n, fn);
 }
 
+// any nonzero byte in p[0..n)
+static bool any_nonzero(const uint8_t* p, int n) {
+  uint64_t acc = 0;
+  int i = 0;
+  for (; i + 8 <= n; i += 8) {
+    uint64_t v;
+    std::memcpy(&v, p + i, 8);
+    acc |= v;
+  }
+  for (; i < n; ++i) acc |= p[i];
+  return acc != 0;
+}
+
 // Group 0 runs on the plan's stream; groups 1.. on non-blocking streams of
 // their own (default priority), each with a join event, created on first use.
 static int ensure_group_streams(fse_plan_s* pl, int G) {
@@ -272,6 +285,7 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
   int rc = FSE_OK;
   // per-frame I/O descriptors; block flags of all frames in one array
   std::vector<IoDesc> io(n);
+  std::vector<uint8_t> host_flags;  // host frames: lost-block flags from the staged masks
   std::vector<int64_t> fout_off(n, -1);
   int64_t flag_total = 0, max_pixels = 0, fout_bytes = 0;
   for (int f = 0; f < n; ++f) {
@@ -298,23 +312,41 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
         (rc = pl->u8_out.reserve(total)) || (fout_bytes && (rc = pl->fout.reserve(fout_bytes))) ||
         (rc = pl->pin_in.reserve(2 * total)) || (rc = pl->pin_out.reserve(total)))
       return rc;
-    // host frames: rows into pinned staging on host threads, then one DMA per
-    // arena (pageable 2-D copies would go row by row)
+    // host frames: rows into pinned staging on host threads, each frame's
+    // DMA issued as soon as its rows are in (pageable 2-D copies would go row
+    // by row), and the lost-block flags taken from the staged mask on the
+    // host, so the schedule does not wait for the device
     uint8_t* pimg = (uint8_t*)pl->pin_in.ptr;
     uint8_t* plost = pimg + total;
+    host_flags.assign(flag_total, 0);
+    std::vector<int> frc(n, FSE_OK);
     parallel_for(pl, n, [&](int f) {
       const fse_frame& fr = frames[f];
       const int H = fr.height, W = fr.width;
       uint8_t* a = pimg + fd[f].off;
       uint8_t* b = plost + fd[f].off;
+      uint8_t* fl = host_flags.data() + io[f].flag_off;
       for (int y = 0; y < H; ++y) {
         std::memcpy(a + (int64_t)y * W, fr.image + (int64_t)y * fr.stride, W);
-        std::memcpy(b + (int64_t)y * W, fr.lost + (int64_t)y * fr.lost_stride, W);
+        uint8_t* row = b + (int64_t)y * W;
+        std::memcpy(row, fr.lost + (int64_t)y * fr.lost_stride, W);
+        uint8_t* frow = fl + (int64_t)((y + goy) / Bh) * wb[f];
+        for (int bj = 0; bj < wb[f]; ++bj) {
+          if (frow[bj]) continue;
+          const int x0 = std::max(0, bj * Bw - gox), x1 = std::min(W, (bj + 1) * Bw - gox);
+          if (x1 > x0 && any_nonzero(row + x0, x1 - x0)) frow[bj] = 1;
+        }
       }
+      const size_t bytes = (size_t)H * W;
+      if (hipSetDevice(pl->device) != hipSuccess ||
+          hipMemcpyAsync((uint8_t*)pl->u8_img.ptr + fd[f].off, a, bytes, hipMemcpyHostToDevice,
+                         s) != hipSuccess ||
+          hipMemcpyAsync((uint8_t*)pl->u8_lost.ptr + fd[f].off, b, bytes, hipMemcpyHostToDevice,
+                         s) != hipSuccess)
+        frc[f] = FSE_ERR_DEVICE;
     });
-    if ((rc = chk(hipMemcpyAsync(pl->u8_img.ptr, pimg, total, hipMemcpyHostToDevice, s))) ||
-        (rc = chk(hipMemcpyAsync(pl->u8_lost.ptr, plost, total, hipMemcpyHostToDevice, s))))
-      return rc;
+    for (int f = 0; f < n; ++f)
+      if (frc[f]) return frc[f];
   }
   T* work = (T*)pl->work.ptr;
   uint8_t* state = (uint8_t*)pl->state.ptr;
@@ -344,17 +376,24 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
   }
   if ((rc = chk(hipMemcpyAsync(pl->io_dev.ptr, io.data(), n * sizeof(IoDesc),
                                hipMemcpyHostToDevice, s))) ||
-      (rc = chk(hipMemsetAsync(pl->flags_dev.ptr, 0, flag_total, s))) ||
+      (dev && (rc = chk(hipMemsetAsync(pl->flags_dev.ptr, 0, flag_total, s)))) ||
       (rc = chk(launch_init<T>((const IoDesc*)pl->io_dev.ptr, n, max_pixels, work, state,
-                               (uint8_t*)pl->flags_dev.ptr, Bh, Bw, gox, goy, s))))
+                               dev ? (uint8_t*)pl->flags_dev.ptr : nullptr, Bh, Bw, gox, goy,
+                               s))))
     return rc;
-  std::vector<uint8_t> allflags(flag_total);
-  if ((rc = chk(hipMemcpyAsync(allflags.data(), pl->flags_dev.ptr, flag_total,
-                               hipMemcpyDeviceToHost, s))) ||
-      (rc = chk(hipStreamSynchronize(s))))
-    return rc;
+  // device frames: the init launch marks the lost blocks; host frames have
+  // their flags already
+  std::vector<uint8_t> allflags;
+  if (dev) {
+    allflags.resize(flag_total);
+    if ((rc = chk(hipMemcpyAsync(allflags.data(), pl->flags_dev.ptr, flag_total,
+                                 hipMemcpyDeviceToHost, s))) ||
+        (rc = chk(hipStreamSynchronize(s))))
+      return rc;
+  }
+  const uint8_t* flag_base = dev ? allflags.data() : host_flags.data();
   std::vector<const uint8_t*> flags(n);
-  for (int f = 0; f < n; ++f) flags[f] = allflags.data() + io[f].flag_off;
+  for (int f = 0; f < n; ++f) flags[f] = flag_base + io[f].flag_off;
 
   // processing order per frame
   std::vector<std::vector<int32_t>> wave_of(n), seq(n);
