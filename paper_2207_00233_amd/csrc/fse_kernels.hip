@@ -533,6 +533,28 @@ __device__ __forceinline__ float forward_transforms_mx(unsigned char* smem, cons
   const int kq = 8 * (lane >> 4);  // first k of the lane's fragments
   const int rq = 4 * (lane >> 4);  // first D row of the lane
 
+  // x is scaled by 2^-xe so that |x| <= 256 (|x| <= |f| since w <= 1): row
+  // sums of at most 64 samples then stay below 2^14 and Yz below 2^15 in f16.
+  // 8-bit data give xe = 0; larger reconstructed samples are scaled exactly.
+  int xe = 0;
+  {
+    float fm = 0.f;
+    for (int i = threadIdx.x; i < M * N; i += 64 * WAVES) {
+      const int m = i / N, n = i - m * N;
+      if (cs[m * NP + n]) fm = fmaxf(fm, fabsf((float)fs[m * NP + n]));
+    }
+    Slot* slots = reinterpret_cast<Slot*>(smem + L.slots);
+    const unsigned wm = wave_max(__float_as_uint(fm));  // non-negative: bits order as values
+    if (lane == 0) slots[wave].key = wm;  // gather_area's readers use .e only
+    __syncthreads();
+    unsigned bm = slots[0].key;
+#pragma unroll
+    for (int q = 1; q < WAVES; ++q) bm = max(bm, slots[q].key);
+    const float xmax = __uint_as_float(bm);
+    if (xmax > 256.f) (void)frexpf(xmax * (1.f / 256.f), &xe);
+  }
+  const float xs_ = ldexpf(1.f, -xe);
+
   // ---- B': row DFTs ----
   f32x4 dx[4], dw[4];
 #pragma unroll
@@ -549,7 +571,7 @@ __device__ __forceinline__ float forward_transforms_mx(unsigned char* smem, cons
           const uint8_t c = cs[m * NP + n];
           const float r = radial[m * N + n];
           wv = c == 1 ? r : (c == 2 ? r * delta : 0.f);
-          xv = (float)fs[m * NP + n] * wv;
+          xv = (float)fs[m * NP + n] * wv * xs_;
         }
         split_f16(xv, xh, xl, e);
         split_f16(wv, wh, wl, e);
@@ -668,7 +690,7 @@ __device__ __forceinline__ float forward_transforms_mx(unsigned char* smem, cons
   __syncthreads();
   // unpack: X[k] = (Z[k] + conj Z[-k]) / 2, W[k] = (Z[k] - conj Z[-k]) / (2 j s)
   {
-    const float h = 0.5f, hs = 0.5f / zscale;
+    const float h = ldexpf(0.5f, xe), hs = 0.5f / zscale;  // X back to scale 1
 #pragma unroll
     for (int j = 0; j < ROWS; ++j) {
       const int k1 = row_of<WAVES, true>(wave, j);

@@ -205,6 +205,29 @@ def test_f16x3_free_running_and_batch_identity():
     np.testing.assert_array_equal(rb.out_f, r.out_f)
 
 
+def test_f16x3_reconstructed_samples_above_256():
+    """A bright square-wave texture whose extrapolation overshoots 256: later
+    blocks read reconstructed samples above 256, which the f16 transforms
+    scale down by a power of two (and back) to keep every operand in range."""
+    rng = np.random.default_rng(3)
+    yy, xx = np.mgrid[0:96, 0:96]
+    img = np.clip(200 + 60 * np.sign(np.sin(2 * np.pi * xx / 7.0) * np.sin(2 * np.pi * yy / 9.0)),
+                  0, 255).astype(np.uint8)
+    lost = synth.slice_loss(rng, 96, 96, 16, (0.3, 0.5))
+    p = fse.Params(border_d=14, iterations=200, precision=fse.FSE_FP32_F16X3)
+    r, _ = check_free_running(p, img, lost, None, PSNR_GAP)
+    assert r.out_f[lost.astype(bool)].max() > 256.0  # the scaled path ran
+    op = oracle_params(p)
+    _, wave_of, seq = oracle.schedule(lost.reshape(6, 16, 6, 16).any(axis=(1, 3)).astype(np.uint8))
+    errs = np.array([np.abs(np.subtract(*teacher_forced_block(
+        img, lost, r.out_f.astype(np.float64), wave_of, op, b // 6, b % 6)[:2])).max()
+        for b in seq])
+    print(f"[parity] f16x3 bright texture: teacher-forced median {np.median(errs):.3e} "
+          f"max {errs.max():.3e} over {len(seq)} blocks", flush=True)
+    assert np.median(errs) <= 0.05
+    assert np.mean(errs <= FP32_TOL) >= 0.9
+
+
 # ------------------------------------------------------------ edge cases
 
 def test_no_losses_is_identity():
