@@ -462,9 +462,10 @@ __device__ __forceinline__ T forward_transforms(unsigned char* smem, const LdsLa
 // float accumulation.  Every operand v is split as v ~ hi + lo with
 // hi = f16(v), lo = f16(v - hi) (about 22 significant bits), and a product of
 // two split operands takes the three tiles hi*hi, hi*lo, lo*hi.  The operands
-// stay inside the f16 range: area samples are 8-bit values times weights <= 1,
-// row sums over at most 64 samples stay below 2^15, twiddles are <= 1, and a
-// lo part that falls below the normal range keeps an absolute error of 2^-24.
+// stay inside the f16 range: x is scaled by a power of two to |x| <= 256
+// (weights and twiddles are <= 1), so row sums over at most 64 samples stay
+// below 2^15, and a lo part that falls below the normal range keeps an
+// absolute error of 2^-24.
 // (Two bf16 parts carry only ~16 bits: measured, that split flipped too many
 // near-tied selections.)  Tile layout (16x16x32): lane l holds row l % 16 of A
 // and column l % 16 of B at k = 8 (l / 16) .. + 7, and column l % 16 of D at
