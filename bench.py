@@ -84,7 +84,14 @@ def cpu_baseline(frames, budget_s=15.0):
         if time.perf_counter() - t0 >= budget_s:
             break
     dt = time.perf_counter() - t0
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {"value": blocks / dt, "unit": "lost blocks/s", "cores": cores, "kind": "oracle",
+            "cpu_model": model,
             "sample": f"{len(used)} whole frames of the batch ({', '.join(sorted(set(used)))}), "
                       f"{blocks} lost blocks, {dt:.1f} s, FP64, K={K_ITER}"}
 
@@ -164,20 +171,29 @@ def subblock_order_gpu(fse, synth, precision, size=512, seeds=(0, 1, 2, 3),
 
 
 def order_comparison_oracle(frames):
-    """The same comparison computed by the FP64 oracle (all host cores)."""
+    """The same comparison computed by the FP64 oracle on all host cores
+    (threads over the blocks of a wave, as in the paper's Section 3).  The
+    line scan has one block per wave, so it runs on one core; the ratio of
+    the two times is the paper's parallelization gain (its Fig. 4: up to 7.7
+    on 8 cores) on this host."""
     import oracle
     cores = len(os.sched_getaffinity(0))
     res = {}
     for name, order in (("optimized", 0), ("line_scan", 1)):
         p = oracle.Params(border_d=BORDER, iterations=K_ITER, nthreads=cores, order=order)
-        psnrs, waves = [], []
+        psnrs, waves, dt = [], [], 0.0
         for fr in frames:
+            t0 = time.perf_counter()
             o = oracle.conceal(p, fr.image, fr.lost)
+            dt += time.perf_counter() - t0
             q = np.where(fr.lost.astype(bool), np.clip(np.rint(o.image), 0, 255), fr.image)
             psnrs.append(psnr_lost(q.astype(np.uint8), fr.image, fr.lost))
             waves.append(int(o.waves))
-        res[name] = {"psnr_db": psnrs, "mean_psnr_db": float(np.mean(psnrs)), "waves": waves}
+        res[name] = {"psnr_db": psnrs, "mean_psnr_db": float(np.mean(psnrs)), "waves": waves,
+                     "s_per_frame": dt / len(frames)}
     res["gain_db"] = res["optimized"]["mean_psnr_db"] - res["line_scan"]["mean_psnr_db"]
+    res["parallelization_gain"] = res["line_scan"]["s_per_frame"] / res["optimized"]["s_per_frame"]
+    res["cores"] = cores
     return res
 
 
@@ -443,8 +459,10 @@ def main():
             cpu["order_comparison_256"] = {"frames": "one 256x256 frame (seed 0), p = 0.25",
                                            **order_comparison_oracle(small)}
             order["gpu_256"] = order_comparison_gpu(fse, small, head_prec, reps=1)
-            log(f"[bench] order comparison: gain {cpu['order_comparison_256']['gain_db']:.3f} dB "
-                f"(oracle), {order['gpu_256']['gain_db']:.3f} dB (GPU), 256x256")
+            oc = cpu["order_comparison_256"]
+            log(f"[bench] order comparison: gain {oc['gain_db']:.3f} dB (oracle), "
+                f"{order['gpu_256']['gain_db']:.3f} dB (GPU), 256x256; oracle parallelization "
+                f"gain {oc['parallelization_gain']:.2f} on {oc['cores']} cores")
 
     line = {
         "metric": "lost blocks extrapolated/s (K=200) + p99 frame latency, FP32 batched vs FP64 plain",
