@@ -720,6 +720,16 @@ __device__ __forceinline__ void load_twiddles(unsigned char* smem, const LdsLayo
   }
 }
 
+// 64 x (cos, sin)(2 pi t / 64) in double, in constant memory: the FP64
+// transform pass indexes it with wave-uniform t only, so its reads are
+// scalar loads instead of LDS reads and address moves.  Written at plan
+// creation (the same values as BlockArgs::twid64).
+__constant__ double c_twid64[2 * kFft];
+
+hipError_t upload_twiddle_constants(const double* tbl) {
+  return hipMemcpyToSymbol(HIP_SYMBOL(c_twid64), tbl, 2 * kFft * sizeof(double));
+}
+
 // FP64 transform pass of the re-rank mode: writes R0 = DFT(x), W = DFT(w)
 // and W0 of every work item in double to BlockArgs::spec64 (the iteration
 // kernel runs in float).  4 wavefronts.
@@ -753,7 +763,6 @@ __global__ __launch_bounds__(256, 3) void fse_dft64_kernel(BlockArgs<float> a,
   const int bi = bij >> 16, bj = bij & 0xffff;
   const FrameDesc fd = a.frames[fr];
   const int by0 = bi * a.Bh - a.goy, bx0 = bj * a.Bw - a.gox;
-  load_twiddles<double>(smem, L, a.twid64);
   const double W0 = gather_area<double, float, WAVES, false>(
       smem, L, M, N, radial64, a.delta64, a.work + fd.off, a.state + fd.off, fd.H, fd.W,
       by0 - a.d, bx0 - a.d, lane, wave);
@@ -762,7 +771,7 @@ __global__ __launch_bounds__(256, 3) void fse_dft64_kernel(BlockArgs<float> a,
   if (!(W0 > 0.0)) return;  // uniform
   const double* xs = reinterpret_cast<const double*>(smem);  // staged x = f w, then w
   const double* ws = xs + M * NP;
-  const double* twt = reinterpret_cast<const double*>(smem + L.twt);
+  const double* twt = c_twid64;  // wave-uniform indices: scalar loads
   double* bx = reinterpret_cast<double*>(smem + L.bx);
   double* bw = reinterpret_cast<double*>(smem + L.bw);
   double* zx = reinterpret_cast<double*>(smem);                 // C exchange

@@ -28,6 +28,7 @@ namespace fse {
 
 template <typename T>
 hipError_t launch_block(const BlockArgs<T>& a, int n_items, int waves, hipStream_t s, int mode);
+hipError_t upload_twiddle_constants(const double* tbl);
 hipError_t launch_dft64(const BlockArgs<float>& a, const double* radial64, int n_items,
                         hipStream_t s);
 template <typename T>
@@ -166,6 +167,9 @@ int plan_device_init(fse_plan_s* pl) {
       return FSE_ERR_DEVICE;
   }
   if (hipMemcpy(pl->tbl_twid64.ptr, pl->twid.data(), 2 * kFft * sizeof(double), hipMemcpyHostToDevice))
+    return FSE_ERR_DEVICE;
+  // the constant-memory copy of the FP64 pass (same values for every plan)
+  if (pl->p.precision == FSE_FP32_RERANK && upload_twiddle_constants(pl->twid.data()) != hipSuccess)
     return FSE_ERR_DEVICE;
   return FSE_OK;
 }
