@@ -35,6 +35,29 @@ namespace fse {
 
 __device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// 64 x (cos, sin)(2 pi t / 64) in double and in float, in constant memory:
+// the transforms index them with wave-uniform t only, so the reads are
+// scalar loads whose values the FMAs take straight from SGPRs (no LDS reads
+// or address moves).  Written at plan creation, the same values as
+// BlockArgs::twid64 / twid.
+__constant__ double c_twid64[2 * kFft];
+__constant__ float c_twid32[2 * kFft];
+
+template <typename T>
+__device__ __forceinline__ const T* twiddle_const();
+template <>
+__device__ __forceinline__ const double* twiddle_const<double>() { return c_twid64; }
+template <>
+__device__ __forceinline__ const float* twiddle_const<float>() { return c_twid32; }
+
+hipError_t upload_twiddle_constants(const double* tbl) {
+  float t32[2 * kFft];
+  for (int i = 0; i < 2 * kFft; ++i) t32[i] = (float)tbl[i];
+  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_twid64), tbl, 2 * kFft * sizeof(double));
+  if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_twid32), t32, sizeof(t32));
+  return e;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
@@ -314,7 +337,7 @@ __device__ __forceinline__ T forward_transforms(unsigned char* smem, const LdsLa
   T* bx = reinterpret_cast<T*>(smem + L.bx);
   T* bw = reinterpret_cast<T*>(smem + L.bw);
   T* Zl = reinterpret_cast<T*>(smem);  // 64 x 64 complex, after phase B
-  T* twt = reinterpret_cast<T*>(smem + L.twt);
+  const T* twt = twiddle_const<T>();  // wave-uniform indices: scalar loads
 
   const T W0 = gather_area<T, TI, WAVES>(smem, L, M, N, radial, delta, img, st, H, W, oy, ox,
                                          lane, wave);
@@ -718,16 +741,6 @@ __device__ __forceinline__ void load_twiddles(unsigned char* smem, const LdsLayo
     reinterpret_cast<double*>(smem + L.tw64)[tid] = v;
     if (with_t) reinterpret_cast<T*>(smem + L.twt)[tid] = (T)v;
   }
-}
-
-// 64 x (cos, sin)(2 pi t / 64) in double, in constant memory: the FP64
-// transform pass indexes it with wave-uniform t only, so its reads are
-// scalar loads instead of LDS reads and address moves.  Written at plan
-// creation (the same values as BlockArgs::twid64).
-__constant__ double c_twid64[2 * kFft];
-
-hipError_t upload_twiddle_constants(const double* tbl) {
-  return hipMemcpyToSymbol(HIP_SYMBOL(c_twid64), tbl, 2 * kFft * sizeof(double));
 }
 
 // FP64 transform pass of the re-rank mode: writes R0 = DFT(x), W = DFT(w)

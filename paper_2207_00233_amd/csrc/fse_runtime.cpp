@@ -168,9 +168,8 @@ int plan_device_init(fse_plan_s* pl) {
   }
   if (hipMemcpy(pl->tbl_twid64.ptr, pl->twid.data(), 2 * kFft * sizeof(double), hipMemcpyHostToDevice))
     return FSE_ERR_DEVICE;
-  // the constant-memory copy of the FP64 pass (same values for every plan)
-  if (pl->p.precision == FSE_FP32_RERANK && upload_twiddle_constants(pl->twid.data()) != hipSuccess)
-    return FSE_ERR_DEVICE;
+  // the constant-memory copies of the transforms (same values for every plan)
+  if (upload_twiddle_constants(pl->twid.data()) != hipSuccess) return FSE_ERR_DEVICE;
   return FSE_OK;
 }
 
