@@ -268,8 +268,6 @@ __device__ __forceinline__ T gather_area(unsigned char* smem, const LdsLayout& L
                                          const T* radial, T delta, const TI* img,
                                          const uint8_t* st, int H, int W, int oy, int ox,
                                          int lane, int wave) {
-  constexpr int THREADS = 64 * WAVES;
-  const int tid = threadIdx.x;
   const int NP = N | 1;
   T* xs = reinterpret_cast<T*>(smem);
   T* ws = xs + M * NP;
@@ -277,19 +275,23 @@ __device__ __forceinline__ T gather_area(unsigned char* smem, const LdsLayout& L
   uint8_t* cs = reinterpret_cast<uint8_t*>(smem + L.cs);
   Slot* slots = reinterpret_cast<Slot*>(smem + L.slots);
   T wsum = T(0);
-  for (int i = tid; i < M * N; i += THREADS) {
-    const int m = i / N, n = i - m * N;
-    const int y = oy + m, x = ox + n;
+  // rows by wavefront, one column per lane (N <= 64): no index division
+  const int n = lane;
+  const int x = ox + n;
+  const bool xin = n < N && x >= 0 && x < W;
+  for (int m = wave; m < M; m += WAVES) {
+    if (n >= N) continue;
+    const int y = oy + m;
     T wv = T(0);
     TI f = TI(0);
     uint8_t c = 0;
-    if (y >= 0 && y < H && x >= 0 && x < W) {
+    if (xin && y >= 0 && y < H) {
       const int64_t p = (int64_t)y * W + x;
       const uint8_t s = st[p];
       const T fac = s == kKnown ? T(1) : (s == kRecon ? delta : T(0));
       c = s == kKnown ? 1 : (s == kRecon ? 2 : 0);
       f = img[p];
-      wv = radial[i] * fac;
+      wv = radial[m * N + n] * fac;
     }
     if constexpr (COMPACT) {
       fs[m * NP + n] = f;
@@ -563,10 +565,9 @@ __device__ __forceinline__ float forward_transforms_mx(unsigned char* smem, cons
   int xe = 0;
   {
     float fm = 0.f;
-    for (int i = threadIdx.x; i < M * N; i += 64 * WAVES) {
-      const int m = i / N, n = i - m * N;
-      if (cs[m * NP + n]) fm = fmaxf(fm, fabsf((float)fs[m * NP + n]));
-    }
+    if (lane < N)
+      for (int m = wave; m < M; m += WAVES)
+        if (cs[m * NP + lane]) fm = fmaxf(fm, fabsf((float)fs[m * NP + lane]));
     Slot* slots = reinterpret_cast<Slot*>(smem + L.slots);
     const unsigned wm = wave_max(__float_as_uint(fm));  // non-negative: bits order as values
     if (lane == 0) slots[wave].key = wm;  // gather_area's readers use .e only
