@@ -39,10 +39,17 @@ PEAK_FP32_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (non-
 PEAK_FP32_PUBLISHED = 157.3
 
 
+# sources whose change invalidates a committed traffic measurement: the
+# kernels and the host code that chooses their launches
+TRAFFIC_SOURCES = ("paper_2207_00233_amd/csrc/fse_kernels.hip", "paper_2207_00233_amd/csrc/fse_device.h",
+                   "paper_2207_00233_amd/csrc/fse_runtime.cpp", "paper_2207_00233_amd/csrc/fse_internal.h")
+
+
 def measured_traffic(precision):
     """HBM bytes of the block kernel over one step (all its launches) from the
     committed rocprofv3 FETCH_SIZE/WRITE_SIZE measurement, if it was taken on
-    this kernel source and precision; None otherwise."""
+    this kernel source, launch configuration (host runtime) and precision;
+    None otherwise."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "fse_block_kernel_traffic.json")
     try:
@@ -50,7 +57,7 @@ def measured_traffic(precision):
     except (OSError, ValueError):
         return None
     h = hashlib.sha256()
-    for fn in ("paper_2207_00233_amd/csrc/fse_kernels.hip", "paper_2207_00233_amd/csrc/fse_device.h"):
+    for fn in TRAFFIC_SOURCES:
         h.update(open(os.path.join(ROOT, fn), "rb").read())
     if rec.get("precision") != precision or rec.get("kernel_source_sha256") != h.hexdigest():
         return None
@@ -497,8 +504,8 @@ def main():
                                       "of different frame groups overlap",
                      "traffic_note": "HBM bytes of the kernel per step (all launches) from "
                                      "rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0 (copy-"
-                                     "calibrated), taken on this kernel source; null when the "
-                                     "source changed since",
+                                     "calibrated), taken on this kernel source and launch "
+                                     "configuration; null when either changed since",
                      "frac_of_published_fp32_peak": achieved / PEAK_FP32_PUBLISHED},
         "fp64_plain": fp64,
         "precision_sweep": sweep,

@@ -147,9 +147,11 @@ typedef struct {
  * call (default 3 in FSE_FP32_RERANK, 4 when the process runs with
  * GPU_MAX_HW_QUEUES >= 8, else 2).  FSE_CRIT_DEPTH=c (0..1):
  * frames whose schedule has at least c times the waves of the deepest frame
- * form a group of their own with the launch shape of their own size and a
- * raised wave priority (FSE_CRIT_PRIO=0 keeps the default priority); 0 = off,
- * default 0.9 in FSE_FP32_RERANK, else off.  None of these changes results
+ * form a group of their own, whose workgroups raise their wave priority
+ * (FSE_CRIT_PRIO=0 keeps the default priority); 0 = off, default 0.9 in
+ * FSE_FP32_RERANK, else off.  FSE_CRIT_WAVES=w (4, 8 or 16;
+ * 0 = by that group's launch size) sets the wavefronts per block of that
+ * group (default 4 in FSE_FP32_RERANK).  None of these changes results
  * beyond the per-shape rounding noted above.
  */
 int32_t fse_plan(const fse_params *p, void *hip_stream, fse_plan_t *out);
@@ -239,7 +241,11 @@ int32_t fse_last_call_stats(fse_plan_t plan, fse_call_stats *out);
  *   crit_depth         frames with at least this fraction of the deepest
  *                      frame's waves form group 0 (0 = off, at most 1); < 0 =
  *                      by precision (0.9 in FSE_FP32_RERANK, else off);
- *   crit_prio          1: group 0's workgroups raise their wave priority.
+ *   crit_prio          1: group 0's workgroups raise their wave priority;
+ *   crit_waves         wavefronts per block of group 0's launches: 4, 8 or
+ *                      16; 0 = by the thresholds above on group 0's own
+ *                      launch size; < 0 = by precision (4 in
+ *                      FSE_FP32_RERANK).
  * FSE_FP32_F16X3 runs every launch on 4 wavefronts whatever the thresholds.
  * fse_plan_get_tuning reports the values in effect (defaults resolved);
  * fse_plan_set_tuning takes effect for launches issued after it returns
@@ -253,6 +259,7 @@ typedef struct {
   int32_t frame_groups;
   double crit_depth;
   int32_t crit_prio;
+  int32_t crit_waves;
 } fse_tuning;
 int32_t fse_plan_get_tuning(fse_plan_t plan, fse_tuning *out);
 int32_t fse_plan_set_tuning(fse_plan_t plan, const fse_tuning *t);

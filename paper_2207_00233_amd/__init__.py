@@ -103,10 +103,11 @@ class _CallStats(ctypes.Structure):
 class _Tuning(ctypes.Structure):
     _fields_ = [("wave_threshold_16", ctypes.c_int32), ("wave_threshold_8", ctypes.c_int32),
                 ("frame_groups", ctypes.c_int32), ("crit_depth", ctypes.c_double),
-                ("crit_prio", ctypes.c_int32)]
+                ("crit_prio", ctypes.c_int32), ("crit_waves", ctypes.c_int32)]
 
 
-TUNING_KEYS = ("wave_threshold_16", "wave_threshold_8", "frame_groups", "crit_depth", "crit_prio")
+TUNING_KEYS = ("wave_threshold_16", "wave_threshold_8", "frame_groups", "crit_depth", "crit_prio",
+               "crit_waves")
 
 
 @dataclasses.dataclass

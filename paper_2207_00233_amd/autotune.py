@@ -1,5 +1,6 @@
 """Launch autotuner: times batched calls of a plan over a grid of launch
-tunings (workgroup-shape threshold, frame groups, critical group; see
+tunings (workgroup-shape threshold, frame groups, critical group and its
+workgroup shape; see
 fse_plan_set_tuning in include/fse.h) on the caller's own frames, and leaves
 the fastest one set on the plan.  Tuning changes how the work is laid on the
 GPU, not what is computed (results stay within the per-shape rounding).
@@ -21,6 +22,7 @@ DEFAULT_GRID: Dict[str, Sequence] = {
     "wave_threshold_16": (128, 256, 512),
     "frame_groups": (1, 2, 3, 4),
     "crit_depth": (0.0, 0.75, 0.9),
+    "crit_waves": (0, 4),
 }
 
 
@@ -50,9 +52,12 @@ def autotune(plan, run: Callable[[], object], grid: Optional[Dict[str, Sequence]
     for vals in itertools.product(*(grid[k] for k in keys)):
         t = dict(base)
         t.update(zip(keys, vals))
-        # with one group there is no critical group: such tunings coincide
+        # with one group, or crit_depth 0, there is no critical group: such
+        # tunings coincide whatever their critical-group fields
+        crit = t["frame_groups"] > 1 and t["crit_depth"] > 0.0
         key = (t["wave_threshold_16"], t["wave_threshold_8"], t["frame_groups"],
-               0.0 if t["frame_groups"] == 1 else t["crit_depth"], t["crit_prio"])
+               t["crit_depth"] if crit else 0.0, t["crit_prio"] if crit else 0,
+               t["crit_waves"] if crit else 0)
         if key in seen:
             continue
         seen.add(key)

@@ -102,10 +102,10 @@ struct fse_plan_s {
   }
   // frames whose schedule has at least crit_depth() x the waves of the
   // deepest frame of a batch form group 0 (when there are other frames): their
-  // chain of waves bounds the batch, so their launches take the wavefront
-  // count of their own size (small launches -> 16 wavefronts, shorter
-  // iterations) instead of the step total's, and their workgroups raise their
-  // wave priority (crit_prio).  0 = off; < 0 = by precision, measured on
+  // chain of waves bounds the batch, so they start first, their launches take
+  // a wavefront count of their own (crit_waves) instead of the step total's,
+  // and their workgroups raise their wave priority (crit_prio).  0 = off;
+  // < 0 = by precision, measured on
   // MI355X with the 64-frame batch: 0.9 for the re-rank mode, whose per-step
   // transform pass lengthens the chain, else off
   std::atomic<double> crit{-1.0};
@@ -114,6 +114,17 @@ struct fse_plan_s {
     return c >= 0.0 ? c : (p.precision == FSE_FP32_RERANK ? 0.9 : 0.0);
   }
   std::atomic<bool> crit_prio{true};
+  // wavefronts per block of group 0's launches: 4/8/16; 0 = waves_for() of
+  // the group's own launch size; < 0 = by precision, measured on MI355X with
+  // the 64-frame batch: 4 for the re-rank mode (16 wavefronts shorten a
+  // block's iterations but cost 1.7x its vector instructions, and group 0
+  // shares the GPU with the other groups)
+  std::atomic<int> crit_waves{-1};
+  int crit_waves_for(int64_t n_items) const {
+    int c = crit_waves.load(std::memory_order_relaxed);
+    if (c < 0) c = p.precision == FSE_FP32_RERANK ? 4 : 0;
+    return c > 0 ? c : waves_for(n_items);
+  }
   std::vector<hipStream_t> gstreams;
   std::vector<hipEvent_t> gjoin;
   // launch cost model used to stagger frames: max(latency, blocks / rate),

@@ -594,7 +594,8 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
       a.trace_u = want_trace ? (int32_t*)pl->trace_u.ptr + i0 * K : nullptr;
       a.trace_dc = want_trace ? (T*)pl->trace_dc.ptr + i0 * K * 2 : nullptr;
       if (rerank) a.spec64 = (double*)pl->spec64.ptr + spec_base[g] * kSpecStride;
-      const int waves = mx ? 4 : pl->waves_for(crit_group && g == 0 ? cnt : step_total);
+      const int waves =
+          mx ? 4 : (crit_group && g == 0 ? pl->crit_waves_for(cnt) : pl->waves_for(step_total));
       if ((rc = chk(hipEventRecord(pl->events[3 * li], gs)))) return rc;
       if constexpr (std::is_same<T, float>::value) {
         if (rerank &&
@@ -777,6 +778,10 @@ int32_t fse_plan(const fse_params* p, void* hip_stream, fse_plan_t* out) {
     if (c >= 0.0 && c <= 1.0) pl->crit = c;
   }
   if (const char* env = std::getenv("FSE_CRIT_PRIO")) pl->crit_prio = std::atoi(env) != 0;
+  if (const char* env = std::getenv("FSE_CRIT_WAVES")) {
+    const int c = std::atoi(env);
+    if (c == 0 || c == 4 || c == 8 || c == 16) pl->crit_waves = c;
+  }
   if (const char* env = std::getenv("FSE_WAVE_THRESHOLDS")) {
     int t16 = 0, t8 = 0;
     if (std::sscanf(env, "%d,%d", &t16, &t8) == 2 && t16 >= 0 && t8 >= 0) {
@@ -863,19 +868,26 @@ int32_t fse_plan_get_tuning(fse_plan_t pl, fse_tuning* out) {
   out->frame_groups = pl->group_count();
   out->crit_depth = pl->crit_depth();
   out->crit_prio = pl->crit_prio.load() ? 1 : 0;
+  {
+    const int c = pl->crit_waves.load();
+    out->crit_waves = c >= 0 ? c : (pl->p.precision == FSE_FP32_RERANK ? 4 : 0);
+  }
   return FSE_OK;
 }
 
 int32_t fse_plan_set_tuning(fse_plan_t pl, const fse_tuning* t) {
   if (!pl || !t) return FSE_ERR_INVALID;
   if (t->wave_threshold_16 < 0 || t->wave_threshold_8 < 0 || t->frame_groups < 0 ||
-      t->frame_groups > 16 || !(t->crit_depth <= 1.0) || (t->crit_prio != 0 && t->crit_prio != 1))
+      t->frame_groups > 16 || !(t->crit_depth <= 1.0) || (t->crit_prio != 0 && t->crit_prio != 1) ||
+      (t->crit_waves >= 0 && t->crit_waves != 0 && t->crit_waves != 4 && t->crit_waves != 8 &&
+       t->crit_waves != 16))
     return FSE_ERR_INVALID;
   pl->wide_threshold = t->wave_threshold_16;
   pl->mid_threshold = t->wave_threshold_8;
   pl->groups = t->frame_groups;
   pl->crit = t->crit_depth < 0.0 ? -1.0 : t->crit_depth;
   pl->crit_prio = t->crit_prio != 0;
+  pl->crit_waves = t->crit_waves < 0 ? -1 : t->crit_waves;
   return FSE_OK;
 }
 

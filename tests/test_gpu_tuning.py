@@ -27,17 +27,18 @@ def test_defaults_and_range_checks():
         t = plan.get_tuning()
         groups = 4 if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) >= 8 else 3
         assert (t["wave_threshold_16"], t["wave_threshold_8"], t["frame_groups"],
-                t["crit_depth"], t["crit_prio"]) == (256, 0, groups, 0.9, 1)
+                t["crit_depth"], t["crit_prio"], t["crit_waves"]) == (256, 0, groups, 0.9, 1, 4)
         for bad in ({"frame_groups": 17}, {"frame_groups": -1}, {"crit_depth": 1.5},
-                    {"wave_threshold_16": -1}, {"crit_prio": 2}):
+                    {"wave_threshold_16": -1}, {"crit_prio": 2}, {"crit_waves": 2},
+                    {"crit_waves": 32}):
             with pytest.raises(fse.FseError):
                 plan.set_tuning(**bad)
         assert plan.get_tuning() == t  # a rejected tuning changes nothing
-        plan.set_tuning(frame_groups=0, crit_depth=-1.0)  # back to "by precision"
+        plan.set_tuning(frame_groups=0, crit_depth=-1.0, crit_waves=-1)  # back to "by precision"
         assert plan.get_tuning() == t
     with fse.Plan(fse.Params(precision=fse.FSE_FP32)) as plan:
         t = plan.get_tuning()
-        assert (t["frame_groups"], t["crit_depth"]) == (2, 0.0)
+        assert (t["frame_groups"], t["crit_depth"], t["crit_waves"]) == (2, 0.0, 0)
 
 
 @pytest.mark.parametrize("precision", [fse.FSE_FP32_RERANK, fse.FSE_FP32])
@@ -48,7 +49,7 @@ def test_tuning_does_not_change_results(precision):
     with fse.Plan(p) as plan:
         for groups, crit in ((1, 0.0), (4, 0.5), (2, 0.0)):
             plan.set_tuning(wave_threshold_16=0, wave_threshold_8=0, frame_groups=groups,
-                            crit_depth=crit)
+                            crit_depth=crit, crit_waves=4)
             res.append(plan.fse_conceal_image(imgs, losts, want_float=True))
             assert plan.last_call_stats()["groups"] == groups
     for other in res[1:]:
