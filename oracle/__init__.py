@@ -9,6 +9,7 @@ shares nothing with the GPU implementation.
 Functions (see ``fse_oracle.c`` for the readings of the paper they take):
   * :func:`block`     -- FSE over one extrapolation area (Section 2, Eq. 1-2)
   * :func:`schedule`  -- line-scan order or Algorithm 1 (Section 3, Eq. 3)
+  * :func:`schedule_refined` -- the sample-count criterion Section 3 suggests
   * :func:`conceal`   -- a whole image, wave by wave, snapshot semantics
   * :func:`extract_area` -- the area and class map one block sees
 """
@@ -27,7 +28,7 @@ _SRC = os.path.join(_HERE, "fse_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 CLS_A, CLS_R, CLS_BI, CLS_BO, CLS_OUT = 0, 1, 2, 3, 4
-ORDER_OPTIMIZED, ORDER_LINESCAN = 0, 1
+ORDER_OPTIMIZED, ORDER_LINESCAN, ORDER_REFINED = 0, 1, 2
 
 
 def build(force: bool = False) -> str:
@@ -109,6 +110,10 @@ def _load():
         lib.oracle_schedule.argtypes = [ctypes.c_int, ctypes.c_int,
                                         P(ctypes.c_uint8), ctypes.c_int,
                                         P(ctypes.c_int32), P(ctypes.c_int32)]
+        lib.oracle_schedule_refined.restype = ctypes.c_int
+        lib.oracle_schedule_refined.argtypes = [ctypes.c_int, ctypes.c_int,
+                                                P(ctypes.c_int32), ctypes.c_int,
+                                                P(ctypes.c_int32), P(ctypes.c_int32)]
         lib.oracle_conceal.restype = ctypes.c_int
         lib.oracle_conceal.argtypes = [
             P(_Params), ctypes.c_int, ctypes.c_int, P(ctypes.c_double),
@@ -188,6 +193,20 @@ def schedule(lost_blocks: np.ndarray, order: int = ORDER_OPTIMIZED):
                              _ptr(wave, ctypes.c_int32), _ptr(seq, ctypes.c_int32))
     n = int((lb != 0).sum())
     return nw, wave.reshape(hb, wb), seq[:n]
+
+
+def schedule_refined(unknown: np.ndarray, outside: int):
+    """Refined order of a block grid: ``unknown`` holds the lost samples of
+    each block, ``outside`` what a neighbour cell outside the image counts
+    (a whole block).  Returns (waves, wave index per block, sequence)."""
+    lib = _load()
+    u = np.ascontiguousarray(unknown, dtype=np.int32)
+    hb, wb = u.shape
+    wave = np.zeros(hb * wb, np.int32)
+    seq = np.zeros(max(1, hb * wb), np.int32)
+    nw = lib.oracle_schedule_refined(hb, wb, _ptr(u, ctypes.c_int32), int(outside),
+                                     _ptr(wave, ctypes.c_int32), _ptr(seq, ctypes.c_int32))
+    return nw, wave.reshape(hb, wb), seq[:int((u > 0).sum())]
 
 
 @dataclasses.dataclass

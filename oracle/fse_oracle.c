@@ -1,6 +1,7 @@
 /*
  * fse_oracle.c -- plain FP64 CPU oracle for Frequency Selective Extrapolation
- * (FSE) with the line-scan and the optimized (Algorithm 1) processing orders.
+ * (FSE) with the line-scan, the optimized (Algorithm 1) and a refined
+ * (sample-count) processing order.
  *
  * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
  * benchmark's CPU-baseline leg may load this library.  It shares no code,
@@ -19,7 +20,9 @@
  *     compensation factor gamma (Section 4);
  *   - the samples of B_i taken from the model;
  *   - the block processing orders of Section 2 (line scan) and Section 3
- *     (Algorithm 1 with Eq. (3)).
+ *     (Algorithm 1 with Eq. (3)), and the refined criterion that Section 3
+ *     suggests without specifying it (counting the unknown samples of the
+ *     neighbouring blocks instead of the neighbouring blocks with losses).
  *
  * Readings of points the paper leaves open (each is a design decision, not a
  * statement of the paper):
@@ -38,7 +41,16 @@
  *   - N_min is the smallest non-negative N (the printed Eq. (3) reads 0 as
  *     soon as one block is done, which would stall the loop);
  *   - every block of a wave reads the image as it was at the start of the
- *     wave (snapshot semantics).
+ *     wave (snapshot semantics);
+ *   - refined order: N(b) = sum over the 8 neighbours of the number of lost,
+ *     not yet extrapolated samples in that neighbour, where a neighbour cell
+ *     outside the image counts as a whole block of unknown samples (the
+ *     sample-count analogue of the +3 / +5 rim penalty); waves are formed
+ *     exactly as in Algorithm 1 (smallest non-negative N, raster order, no
+ *     two adjacent blocks), and after a wave every pending neighbour of a
+ *     finished block loses that block's unknown samples from its N.  When
+ *     every lost block is lost entirely, N is B_h*B_w times Algorithm 1's N
+ *     and both orders coincide.
  *
  * Projections are explicit separable spatial-domain sums, recomputed from
  * the spatial residual in every iteration.  No FFT, no spectral shortcut.
@@ -66,7 +78,7 @@ typedef struct {
   double delta;               /* reconstructed-area attenuation */
   double gamma;               /* orthogonality deficiency compensation */
   int32_t iterations;         /* K */
-  int32_t order;              /* 0 = optimized (Algorithm 1), 1 = line scan */
+  int32_t order;              /* 0 = optimized (Algorithm 1), 1 = line scan, 2 = refined */
   double empty_fill;          /* value for an area without support */
   int32_t tie_largest;        /* test switch: ties go to the largest index */
   int32_t frame_off_m;        /* test switch: row offset of L in the grid */
@@ -387,6 +399,84 @@ int oracle_schedule(int hb, int wb, const uint8_t *lost, int order,
   return nwaves;
 }
 
+/*
+ * Refined order (the criterion Section 3 mentions as an alternative).
+ * unknown[hb*wb]: lost samples of each block (0 = nothing to extrapolate);
+ * outside: the count a neighbour cell outside the image contributes (a whole
+ * block, B_h*B_w).  Outputs as oracle_schedule.  Returns the number of waves.
+ */
+int oracle_schedule_refined(int hb, int wb, const int32_t *unknown, int outside,
+                            int32_t *wave_of, int32_t *order_out) {
+  if (hb <= 0 || wb <= 0) return 0;
+  int nb = hb * wb, nwaves = 0, pos = 0;
+  long *cnt = (long *)calloc((size_t)nb, sizeof(long));
+  int32_t *left = (int32_t *)malloc(sizeof(int32_t) * nb);  /* samples still unknown */
+  uint8_t *in_s = (uint8_t *)calloc((size_t)nb, 1);
+  for (int b = 0; b < nb; ++b) {
+    wave_of[b] = -1;
+    left[b] = unknown[b];
+  }
+  /* initial N: unknown samples of the 8 neighbours, outside cells whole */
+  for (int i = 0; i < hb; ++i)
+    for (int j = 0; j < wb; ++j) {
+      long n = 0;
+      for (int di = -1; di <= 1; ++di)
+        for (int dj = -1; dj <= 1; ++dj) {
+          if (!di && !dj) continue;
+          int y = i + di, x = j + dj;
+          if (y < 0 || y >= hb || x < 0 || x >= wb)
+            n += outside;
+          else
+            n += left[y * wb + x];
+        }
+      cnt[i * wb + j] = left[i * wb + j] > 0 ? n : -1;
+    }
+  for (;;) {
+    long nmin = -1;
+    for (int b = 0; b < nb; ++b)
+      if (cnt[b] >= 0 && (nmin < 0 || cnt[b] < nmin)) nmin = cnt[b];
+    if (nmin < 0) break;
+    memset(in_s, 0, (size_t)nb);
+    for (int i = 0; i < hb; ++i)
+      for (int j = 0; j < wb; ++j) {
+        if (cnt[i * wb + j] != nmin) continue;
+        int clash = 0;
+        for (int di = -1; di <= 1 && !clash; ++di)
+          for (int dj = -1; dj <= 1; ++dj) {
+            if (!di && !dj) continue;
+            int y = i + di, x = j + dj;
+            if (y < 0 || y >= hb || x < 0 || x >= wb) continue;
+            if (in_s[y * wb + x]) { clash = 1; break; }
+          }
+        if (clash) continue;
+        in_s[i * wb + j] = 1;
+        wave_of[i * wb + j] = nwaves;
+        if (order_out) order_out[pos] = i * wb + j;
+        ++pos;
+      }
+    /* after the wave: the block's samples are known; each pending neighbour
+     * has that many unknown samples fewer around it */
+    for (int b = 0; b < nb; ++b) {
+      if (!in_s[b]) continue;
+      int i = b / wb, j = b % wb;
+      cnt[b] = -1;
+      for (int di = -1; di <= 1; ++di)
+        for (int dj = -1; dj <= 1; ++dj) {
+          if (!di && !dj) continue;
+          int y = i + di, x = j + dj;
+          if (y < 0 || y >= hb || x < 0 || x >= wb) continue;
+          if (cnt[y * wb + x] >= 0) cnt[y * wb + x] -= left[b];
+        }
+      left[b] = 0;
+    }
+    ++nwaves;
+  }
+  free(cnt);
+  free(left);
+  free(in_s);
+  return nwaves;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Whole image                                                              */
 /* ------------------------------------------------------------------------ */
@@ -432,7 +522,7 @@ int oracle_conceal(const oracle_params *p, int H, int W, const double *img,
                    int32_t *trace_u, double *trace_dc) {
   if (H <= 0 || W <= 0 || p->block_w <= 0 || p->block_h <= 0 || p->border_d < 0 ||
       p->grid_off_x < 0 || p->grid_off_x >= p->block_w || p->grid_off_y < 0 ||
-      p->grid_off_y >= p->block_h)
+      p->grid_off_y >= p->block_h || p->order < 0 || p->order > 2)
     return -1;
   const int M = p->block_h + 2 * p->border_d, N = p->block_w + 2 * p->border_d;
   if (M > p->fft_h || N > p->fft_w) return -1;
@@ -440,6 +530,7 @@ int oracle_conceal(const oracle_params *p, int H, int W, const double *img,
   const int wb = (W + p->grid_off_x + p->block_w - 1) / p->block_w;
   const int nb = hb * wb, K = p->iterations;
   uint8_t *blost = (uint8_t *)calloc((size_t)nb, 1);
+  int32_t *bcnt = (int32_t *)calloc((size_t)nb, sizeof(int32_t));  /* lost samples per block */
   uint8_t *state = (uint8_t *)malloc((size_t)H * W);
   uint8_t *snap_state = (uint8_t *)malloc((size_t)H * W);
   double *snap = (double *)malloc(sizeof(double) * H * W);
@@ -450,10 +541,14 @@ int oracle_conceal(const oracle_params *p, int H, int W, const double *img,
       int l = lost[y * W + x] != 0;
       state[y * W + x] = l ? ST_PENDING : ST_KNOWN;
       out[y * W + x] = l ? 0.0 : img[y * W + x];
-      if (l)
-        blost[((y + p->grid_off_y) / p->block_h) * wb + (x + p->grid_off_x) / p->block_w] = 1;
+      if (l) {
+        int b = ((y + p->grid_off_y) / p->block_h) * wb + (x + p->grid_off_x) / p->block_w;
+        blost[b] = 1;
+        bcnt[b] += 1;
+      }
     }
-  int nw = oracle_schedule(hb, wb, blost, p->order, wv, ord);
+  int nw = p->order == 2 ? oracle_schedule_refined(hb, wb, bcnt, p->block_h * p->block_w, wv, ord)
+                         : oracle_schedule(hb, wb, blost, p->order, wv, ord);
   if (wave_of) memcpy(wave_of, wv, sizeof(int32_t) * nb);
   int pos = 0, nlost = 0;
   for (int b = 0; b < nb; ++b) nlost += blost[b] != 0;
@@ -490,7 +585,7 @@ int oracle_conceal(const oracle_params *p, int H, int W, const double *img,
       free(f); free(g); free(cls);
     }
   }
-  free(blost); free(state); free(snap_state); free(snap); free(wv); free(ord);
+  free(blost); free(bcnt); free(state); free(snap_state); free(snap); free(wv); free(ord);
   return nw;
 }
 
