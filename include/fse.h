@@ -54,8 +54,15 @@ extern "C" {
 
 typedef struct fse_plan_s *fse_plan_t; /* opaque, owned by the library */
 
-/* Block processing order: Algorithm 1 (Section 3) or line scan (Section 2). */
-enum { FSE_ORDER_OPTIMIZED = 0, FSE_ORDER_LINESCAN = 1 };
+/* Block processing order: Algorithm 1 (Section 3), line scan (Section 2), or
+ * the refined criterion Section 3 suggests as an alternative: Algorithm 1
+ * with N(b) counting the lost, not yet extrapolated samples of the 8
+ * neighbouring blocks instead of the neighbouring blocks with losses (a
+ * neighbour cell outside the image counts as a whole block of unknown
+ * samples; a finished block's samples leave its neighbours' N).  With
+ * whole-block losses the refined order equals Algorithm 1; with partial
+ * losses it orders by sample counts, usually in more, smaller waves. */
+enum { FSE_ORDER_OPTIMIZED = 0, FSE_ORDER_LINESCAN = 1, FSE_ORDER_REFINED = 2 };
 
 /* Arithmetic of the per-block iteration. */
 enum {
@@ -195,12 +202,24 @@ int32_t fse_poll(fse_plan_t plan, uint64_t ticket, int32_t timeout_us);
 /*
  * Processing order only (paper Algorithm 1 / line scan) for a block grid of
  * hb x wb blocks; lost[hb*wb] nonzero marks blocks with samples to
- * extrapolate.  wave_of[hb*wb] receives the wave index (-1 for the other
+ * extrapolate (FSE_ORDER_REFINED needs sample counts: fse_schedule_refined).  wave_of[hb*wb] receives the wave index (-1 for the other
  * blocks); seq[hb*wb] (nullable) the lost blocks in processing order.
  * Host-only; returns the number of waves (>= 0) or FSE_ERR_INVALID.
  */
 int32_t fse_schedule(int32_t hb, int32_t wb, const uint8_t *lost, int32_t order,
                      int32_t *wave_of, int32_t *seq);
+
+/*
+ * Refined processing order (FSE_ORDER_REFINED) for a block grid of hb x wb
+ * blocks: unknown[hb*wb] holds the number of lost samples of each block (0 =
+ * nothing to extrapolate, negative values count as 0); `outside` (>= 0) is
+ * what a neighbour cell outside the image counts (normally block_w *
+ * block_h).  wave_of and seq as in fse_schedule.  Host-only; returns the
+ * number of waves (>= 0) or FSE_ERR_INVALID (negative size or outside, null
+ * pointer with a non-empty grid).
+ */
+int32_t fse_schedule_refined(int32_t hb, int32_t wb, const int32_t *unknown, int32_t outside,
+                             int32_t *wave_of, int32_t *seq);
 
 /* Statistics of the last fse_conceal_image call.  The frames of a call run
  * in `groups` groups, each as its own sequence of launches (one per step) on

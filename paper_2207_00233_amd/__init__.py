@@ -30,6 +30,7 @@ FSE_ERR_TICKET = -6
 
 FSE_ORDER_OPTIMIZED = 0
 FSE_ORDER_LINESCAN = 1
+FSE_ORDER_REFINED = 2
 FSE_FP64 = 0
 FSE_FP32 = 1
 FSE_FP32_RERANK = 2
@@ -37,8 +38,8 @@ FSE_FP32_F16X3 = 3
 FSE_FLAG_DEVICE_PTRS = 1
 
 EXPORTED = ("fse_plan", "fse_plan_destroy", "fse_conceal_image", "fse_submit",
-            "fse_poll", "fse_schedule", "fse_last_call_stats", "fse_plan_get_tuning",
-            "fse_plan_set_tuning", "fse_strerror")
+            "fse_poll", "fse_schedule", "fse_schedule_refined", "fse_last_call_stats",
+            "fse_plan_get_tuning", "fse_plan_set_tuning", "fse_strerror")
 
 
 class FseError(RuntimeError):
@@ -163,6 +164,9 @@ def load():
     lib.fse_schedule.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                  ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
     lib.fse_schedule.restype = ctypes.c_int32
+    lib.fse_schedule_refined.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                         ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+    lib.fse_schedule_refined.restype = ctypes.c_int32
     lib.fse_last_call_stats.argtypes = [ctypes.c_void_p, P(_CallStats)]
     lib.fse_last_call_stats.restype = ctypes.c_int32
     lib.fse_plan_get_tuning.argtypes = [ctypes.c_void_p, P(_Tuning)]
@@ -199,6 +203,21 @@ def fse_schedule(lost_blocks: np.ndarray, order: int = FSE_ORDER_OPTIMIZED):
     nw = _check(lib.fse_schedule(hb, wb, lb.ctypes.data, order, wave.ctypes.data,
                                  seq.ctypes.data), "fse_schedule")
     return nw, wave.reshape(hb, wb), seq[:int((lb != 0).sum())]
+
+
+def fse_schedule_refined(unknown: np.ndarray, outside: int):
+    """Refined processing order of a block grid (``fse_schedule_refined``):
+    ``unknown`` = lost samples per block, ``outside`` = what a neighbour cell
+    outside the image counts.  Returns (waves, wave index per block, lost
+    blocks in order)."""
+    lib = load()
+    u = np.ascontiguousarray(unknown, dtype=np.int32)
+    hb, wb = u.shape
+    wave = np.zeros(hb * wb, np.int32)
+    seq = np.zeros(max(1, hb * wb), np.int32)
+    nw = _check(lib.fse_schedule_refined(hb, wb, u.ctypes.data, int(outside), wave.ctypes.data,
+                                         seq.ctypes.data), "fse_schedule_refined")
+    return nw, wave.reshape(hb, wb), seq[:int((u > 0).sum())]
 
 
 @dataclasses.dataclass

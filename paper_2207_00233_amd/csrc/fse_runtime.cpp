@@ -37,8 +37,8 @@ hipError_t launch_scatter(T* work, uint8_t* state, const FrameDesc* frames, cons
                           hipStream_t s);
 template <typename T>
 hipError_t launch_init(const IoDesc* io, int nframes, int64_t max_pixels, T* work,
-                       uint8_t* state, uint8_t* flags, int Bh, int Bw, int gox, int goy,
-                       hipStream_t s);
+                       uint8_t* state, uint8_t* flags, int32_t* counts, int Bh, int Bw,
+                       int gox, int goy, hipStream_t s);
 template <typename T>
 hipError_t launch_finalize(const IoDesc* io, int nframes, int64_t max_pixels,
                            const uint8_t* state, const T* work, hipStream_t s);
@@ -93,7 +93,9 @@ int validate_params(const fse_params* p) {
   if (!(p->delta >= 0.0 && p->delta <= 1.0)) return FSE_ERR_INVALID;
   if (!(p->gamma > 0.0 && p->gamma <= 1.0)) return FSE_ERR_INVALID;
   if (p->iterations < 1 || p->iterations > FSE_MAX_ITERATIONS) return FSE_ERR_INVALID;
-  if (p->order != FSE_ORDER_OPTIMIZED && p->order != FSE_ORDER_LINESCAN) return FSE_ERR_INVALID;
+  if (p->order != FSE_ORDER_OPTIMIZED && p->order != FSE_ORDER_LINESCAN &&
+      p->order != FSE_ORDER_REFINED)
+    return FSE_ERR_INVALID;
   if (p->precision != FSE_FP64 && p->precision != FSE_FP32 && p->precision != FSE_FP32_RERANK &&
       p->precision != FSE_FP32_F16X3)
     return FSE_ERR_INVALID;
@@ -237,6 +239,13 @@ static void parallel_for(fse_plan_s* pl, int n, const std::function<void(int)>& 
   pl->pool->run(n, fn);
 }
 
+// nonzero bytes in p[0..n)
+static int count_nonzero(const uint8_t* p, int n) {
+  int c = 0;
+  for (int i = 0; i < n; ++i) c += p[i] != 0;
+  return c;
+}
+
 // any nonzero byte in p[0..n)
 static bool any_nonzero(const uint8_t* p, int n) {
   uint64_t acc = 0;
@@ -289,6 +298,9 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
   // per-frame I/O descriptors; block flags of all frames in one array
   std::vector<IoDesc> io(n);
   std::vector<uint8_t> host_flags;  // host frames: lost-block flags from the staged masks
+  // the refined order needs the lost samples of every block instead of flags
+  const bool refined = p.order == FSE_ORDER_REFINED;
+  std::vector<int32_t> host_counts;
   std::vector<int64_t> fout_off(n, -1);
   int64_t flag_total = 0, max_pixels = 0, fout_bytes = 0;
   for (int f = 0; f < n; ++f) {
@@ -308,7 +320,7 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
   }
   if ((rc = pl->work.reserve(total * sizeof(T))) || (rc = pl->state.reserve(total)) ||
       (rc = pl->frames_dev.reserve(n * sizeof(FrameDesc))) ||
-      (rc = pl->io_dev.reserve(n * sizeof(IoDesc))) || (rc = pl->flags_dev.reserve(flag_total)))
+      (rc = pl->io_dev.reserve(n * sizeof(IoDesc))) || (rc = pl->flags_dev.reserve(flag_total * (refined ? 4 : 1))))
     return rc;
   if (!dev) {
     if ((rc = pl->u8_img.reserve(total)) || (rc = pl->u8_lost.reserve(total)) ||
@@ -321,19 +333,30 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
     // host, so the schedule does not wait for the device
     uint8_t* pimg = (uint8_t*)pl->pin_in.ptr;
     uint8_t* plost = pimg + total;
-    host_flags.assign(flag_total, 0);
+    if (refined)
+      host_counts.assign(flag_total, 0);
+    else
+      host_flags.assign(flag_total, 0);
     std::vector<int> frc(n, FSE_OK);
     parallel_for(pl, n, [&](int f) {
       const fse_frame& fr = frames[f];
       const int H = fr.height, W = fr.width;
       uint8_t* a = pimg + fd[f].off;
       uint8_t* b = plost + fd[f].off;
-      uint8_t* fl = host_flags.data() + io[f].flag_off;
       for (int y = 0; y < H; ++y) {
         std::memcpy(a + (int64_t)y * W, fr.image + (int64_t)y * fr.stride, W);
         uint8_t* row = b + (int64_t)y * W;
         std::memcpy(row, fr.lost + (int64_t)y * fr.lost_stride, W);
-        uint8_t* frow = fl + (int64_t)((y + goy) / Bh) * wb[f];
+        const int64_t rb = io[f].flag_off + (int64_t)((y + goy) / Bh) * wb[f];
+        if (refined) {
+          int32_t* crow = host_counts.data() + rb;
+          for (int bj = 0; bj < wb[f]; ++bj) {
+            const int x0 = std::max(0, bj * Bw - gox), x1 = std::min(W, (bj + 1) * Bw - gox);
+            if (x1 > x0) crow[bj] += count_nonzero(row + x0, x1 - x0);
+          }
+          continue;
+        }
+        uint8_t* frow = host_flags.data() + rb;
         for (int bj = 0; bj < wb[f]; ++bj) {
           if (frow[bj]) continue;
           const int x0 = std::max(0, bj * Bw - gox), x1 = std::min(W, (bj + 1) * Bw - gox);
@@ -379,24 +402,33 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
   }
   if ((rc = chk(hipMemcpyAsync(pl->io_dev.ptr, io.data(), n * sizeof(IoDesc),
                                hipMemcpyHostToDevice, s))) ||
-      (dev && (rc = chk(hipMemsetAsync(pl->flags_dev.ptr, 0, flag_total, s)))) ||
+      (dev && (rc = chk(hipMemsetAsync(pl->flags_dev.ptr, 0, flag_total * (refined ? 4 : 1),
+                                       s)))) ||
       (rc = chk(launch_init<T>((const IoDesc*)pl->io_dev.ptr, n, max_pixels, work, state,
-                               dev ? (uint8_t*)pl->flags_dev.ptr : nullptr, Bh, Bw, gox, goy,
-                               s))))
+                               dev && !refined ? (uint8_t*)pl->flags_dev.ptr : nullptr,
+                               dev && refined ? (int32_t*)pl->flags_dev.ptr : nullptr, Bh, Bw,
+                               gox, goy, s))))
     return rc;
-  // device frames: the init launch marks the lost blocks; host frames have
-  // their flags already
+  // device frames: the init launch marks the lost blocks (or counts their
+  // lost samples); host frames have them already
   std::vector<uint8_t> allflags;
+  std::vector<int32_t> allcounts;
   if (dev) {
-    allflags.resize(flag_total);
-    if ((rc = chk(hipMemcpyAsync(allflags.data(), pl->flags_dev.ptr, flag_total,
+    void* dst = nullptr;
+    if (refined) {
+      allcounts.resize(flag_total);
+      dst = allcounts.data();
+    } else {
+      allflags.resize(flag_total);
+      dst = allflags.data();
+    }
+    if ((rc = chk(hipMemcpyAsync(dst, pl->flags_dev.ptr, flag_total * (refined ? 4 : 1),
                                  hipMemcpyDeviceToHost, s))) ||
         (rc = chk(hipStreamSynchronize(s))))
       return rc;
   }
   const uint8_t* flag_base = dev ? allflags.data() : host_flags.data();
-  std::vector<const uint8_t*> flags(n);
-  for (int f = 0; f < n; ++f) flags[f] = flag_base + io[f].flag_off;
+  const int32_t* count_base = dev ? allcounts.data() : host_counts.data();
 
   // processing order per frame
   std::vector<std::vector<int32_t>> wave_of(n), seq(n);
@@ -404,7 +436,10 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
   std::vector<int> nwaves(n, 0);
   parallel_for(pl, n, [&](int f) {
     wave_of[f].resize((size_t)hb[f] * wb[f]);
-    nwaves[f] = schedule_blocks(hb[f], wb[f], flags[f], p.order, wave_of[f].data(), &seq[f]);
+    nwaves[f] = refined ? schedule_blocks_refined(hb[f], wb[f], count_base + io[f].flag_off,
+                                                  Bh * Bw, wave_of[f].data(), &seq[f])
+                        : schedule_blocks(hb[f], wb[f], flag_base + io[f].flag_off, p.order,
+                                          wave_of[f].data(), &seq[f]);
   });
   for (int f = 0; f < n; ++f) {
     const int nw = nwaves[f];
@@ -857,6 +892,17 @@ int32_t fse_schedule(int32_t hb, int32_t wb, const uint8_t* lost, int32_t order,
   if (hb == 0 || wb == 0) return 0;
   std::vector<int32_t> s;
   int nw = schedule_blocks(hb, wb, lost, order, wave_of, seq ? &s : nullptr);
+  if (seq) std::copy(s.begin(), s.end(), seq);
+  return nw;
+}
+
+int32_t fse_schedule_refined(int32_t hb, int32_t wb, const int32_t* unknown, int32_t outside,
+                             int32_t* wave_of, int32_t* seq) {
+  if (hb < 0 || wb < 0 || outside < 0 || (hb * (int64_t)wb > 0 && (!unknown || !wave_of)))
+    return FSE_ERR_INVALID;
+  if (hb == 0 || wb == 0) return 0;
+  std::vector<int32_t> s;
+  int nw = schedule_blocks_refined(hb, wb, unknown, outside, wave_of, seq ? &s : nullptr);
   if (seq) std::copy(s.begin(), s.end(), seq);
   return nw;
 }

@@ -11,6 +11,12 @@
 // smallest non-negative N and that touches no block already taken for this
 // wave; after the wave every taken block is finished and its pending
 // neighbours lose one not-extrapolated neighbour.
+//
+// Refined order (the alternative criterion Section 3 mentions): N(b) counts
+// the lost, not yet extrapolated samples of the neighbours (a cell outside
+// the image counts a whole block), waves are formed as above, and a finished
+// block's samples leave its pending neighbours' N.  With whole-block losses N
+// is a fixed multiple of Algorithm 1's N and the two orders coincide.
 #include <algorithm>
 #include <cstdint>
 #include <vector>
@@ -103,6 +109,64 @@ int schedule_blocks(int hb, int wb, const uint8_t* lost, int order, int32_t* wav
         }
       }
     }
+    ++wave;
+  }
+  return wave;
+}
+
+int schedule_blocks_refined(int hb, int wb, const int32_t* unknown, int32_t outside,
+                            int32_t* wave_of, std::vector<int32_t>* seq) {
+  const int nb = hb * wb;
+  for (int b = 0; b < nb; ++b) wave_of[b] = -1;
+  if (seq) seq->clear();
+  // padded grid as above: the ring of outside cells holds `outside` unknown
+  // samples that never become known
+  const int W2 = wb + 2, H2 = hb + 2, n2 = W2 * H2;
+  const int nbr[8] = {-W2 - 1, -W2, -W2 + 1, -1, 1, W2 - 1, W2, W2 + 1};
+  std::vector<int64_t> left(n2, outside);  // unknown samples per cell
+  for (int i = 0; i < hb; ++i)
+    for (int j = 0; j < wb; ++j) left[(i + 1) * W2 + j + 1] = std::max(0, unknown[i * wb + j]);
+  // pending cells in raster order of the padded index, with their N
+  std::vector<int32_t> pend;
+  std::vector<int64_t> cnt(n2, -1);
+  for (int i = 1; i <= hb; ++i)
+    for (int j = 1; j <= wb; ++j) {
+      const int p = i * W2 + j;
+      if (left[p] <= 0) continue;
+      int64_t c = 0;
+      for (int k = 0; k < 8; ++k) c += left[p + nbr[k]];
+      cnt[p] = c;
+      pend.push_back(p);
+    }
+  std::vector<uint8_t> blocked(n2, 0);
+  std::vector<int32_t> taken;
+  int wave = 0;
+  while (!pend.empty()) {
+    int64_t nmin = cnt[pend[0]];
+    for (int32_t p : pend) nmin = std::min(nmin, cnt[p]);
+    taken.clear();
+    for (int32_t p : pend) {
+      if (cnt[p] != nmin || blocked[p]) continue;
+      taken.push_back(p);
+      for (int q = 0; q < 8; ++q) blocked[p + nbr[q]] = 1;
+    }
+    for (int32_t p : taken) {
+      const int b = (p / W2 - 1) * wb + (p % W2 - 1);
+      wave_of[b] = wave;
+      if (seq) seq->push_back(b);
+      for (int q = 0; q < 8; ++q) blocked[p + nbr[q]] = 0;
+    }
+    for (int32_t p : taken) {
+      cnt[p] = -1;
+      for (int k = 0; k < 8; ++k) {
+        const int q = p + nbr[k];
+        if (cnt[q] >= 0) cnt[q] -= left[p];
+      }
+      left[p] = 0;
+    }
+    // drop the finished cells, keeping raster order
+    pend.erase(std::remove_if(pend.begin(), pend.end(), [&](int32_t p) { return cnt[p] < 0; }),
+               pend.end());
     ++wave;
   }
   return wave;

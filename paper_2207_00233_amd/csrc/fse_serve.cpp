@@ -2,7 +2,8 @@
 // continuous batching.
 //
 // fse_submit copies the frame into library-owned pinned memory, derives the
-// block flags and the processing order on the caller's thread, and queues it.
+// block flags (lost-sample counts) and the processing order on the caller's
+// thread, and queues it.
 // One worker thread per plan:
 //   - admits queued frames while the device arena (device_mem_budget) and the
 //     slot count (max_inflight_frames) allow, uploads them and builds their
@@ -46,8 +47,8 @@ hipError_t launch_scatter(T* work, uint8_t* state, const FrameDesc* frames, cons
                           hipStream_t s);
 template <typename T>
 hipError_t launch_init(const IoDesc* io, int nframes, int64_t max_pixels, T* work,
-                       uint8_t* state, uint8_t* flags, int Bh, int Bw, int gox, int goy,
-                       hipStream_t s);
+                       uint8_t* state, uint8_t* flags, int32_t* counts, int Bh, int Bw,
+                       int gox, int goy, hipStream_t s);
 template <typename T>
 hipError_t launch_finalize(const IoDesc* io, int nframes, int64_t max_pixels,
                            const uint8_t* state, const T* work, hipStream_t s);
@@ -261,7 +262,7 @@ static int worker_admit(Serving* sv, const std::shared_ptr<Req>& r) {
       hipMemcpyAsync((IoDesc*)sv->d_io.ptr + r->slot, hd + sizeof(fd), sizeof(io),
                      hipMemcpyHostToDevice, s) != hipSuccess)
     return FSE_ERR_DEVICE;
-  if (launch_init<T>((const IoDesc*)sv->d_io.ptr + r->slot, 1, px, work, state, nullptr,
+  if (launch_init<T>((const IoDesc*)sv->d_io.ptr + r->slot, 1, px, work, state, nullptr, nullptr,
                      pl->p.block_h, pl->p.block_w, pl->p.grid_off_x, pl->p.grid_off_y,
                      s) != hipSuccess)
     return FSE_ERR_DEVICE;
@@ -561,7 +562,9 @@ int32_t fse_submit(fse_plan_t pl, const fse_frame* f, uint64_t* ticket) {
     sv->pinned.put(r->pin_out);
     return FSE_ERR_DEVICE;
   }
-  std::vector<uint8_t> flags((size_t)r->hb * r->wb, 0);
+  // lost samples per block (the refined order counts them; the others only
+  // need to know which blocks have any)
+  std::vector<int32_t> counts((size_t)r->hb * r->wb, 0);
   for (int y = 0; y < r->H; ++y) {
     std::memcpy(r->pin_in + (int64_t)y * r->W, f->image + (int64_t)y * f->stride, r->W);
     const uint8_t* lrow = f->lost + (int64_t)y * f->lost_stride;
@@ -577,16 +580,23 @@ int32_t fse_submit(fse_plan_t pl, const fse_frame* f, uint64_t* ticket) {
       }
       for (int q = x; q < x + 8; ++q) {
         dst[q] = lrow[q] ? 1 : 0;
-        if (lrow[q]) flags[(size_t)bi * r->wb + (q + p.grid_off_x) / p.block_w] = 1;
+        if (lrow[q]) counts[(size_t)bi * r->wb + (q + p.grid_off_x) / p.block_w] += 1;
       }
     }
     for (; x < r->W; ++x) {
       dst[x] = lrow[x] ? 1 : 0;
-      if (lrow[x]) flags[(size_t)bi * r->wb + (x + p.grid_off_x) / p.block_w] = 1;
+      if (lrow[x]) counts[(size_t)bi * r->wb + (x + p.grid_off_x) / p.block_w] += 1;
     }
   }
-  std::vector<int32_t> wave_of(flags.size());
-  r->nwaves = schedule_blocks(r->hb, r->wb, flags.data(), p.order, wave_of.data(), &r->seq);
+  std::vector<int32_t> wave_of(counts.size());
+  if (p.order == FSE_ORDER_REFINED) {
+    r->nwaves = schedule_blocks_refined(r->hb, r->wb, counts.data(), p.block_h * p.block_w,
+                                        wave_of.data(), &r->seq);
+  } else {
+    std::vector<uint8_t> flags(counts.size());
+    for (size_t b = 0; b < counts.size(); ++b) flags[b] = counts[b] > 0;
+    r->nwaves = schedule_blocks(r->hb, r->wb, flags.data(), p.order, wave_of.data(), &r->seq);
+  }
   r->wave_start.assign(r->nwaves + 1, 0);
   for (size_t q = 0, t = 0; t <= (size_t)r->nwaves; ++t) {
     while (q < r->seq.size() && wave_of[r->seq[q]] < (int)t) ++q;

@@ -210,6 +210,20 @@ def consecutive_loss(rng: np.random.Generator, height: int, width: int, size: in
     return block_loss_mask(height, width, size, cells)
 
 
+def hole_loss(rng: np.random.Generator, height: int, width: int, n: int,
+              size=(1, 12)) -> np.ndarray:
+    """`n` rectangular holes of U[size] x U[size] samples at uniformly random
+    positions, not aligned to any block grid (losses that leave blocks
+    partially known)."""
+    lost = np.zeros((height, width), np.uint8)
+    for _ in range(n):
+        h, w = (int(v) for v in rng.integers(size[0], size[1] + 1, 2))
+        y = int(rng.integers(0, max(1, height - h + 1)))
+        x = int(rng.integers(0, max(1, width - w + 1)))
+        lost[y:y + h, x:x + w] = 1
+    return lost
+
+
 def mixed_loss(rng: np.random.Generator, height: int, width: int, size: int = 16,
                p_isolated: float = 0.12, runs: int = 6) -> np.ndarray:
     """Isolated size x size losses together with consecutive runs (the

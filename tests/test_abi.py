@@ -79,6 +79,14 @@ def test_null_arguments(lib):
     assert lib.fse_last_call_stats(None, None) == fse.FSE_ERR_INVALID
     assert lib.fse_schedule(2, 2, None, 0, None, None) == fse.FSE_ERR_INVALID
     assert lib.fse_schedule(0, 5, None, 0, None, None) == 0
+    assert lib.fse_schedule(2, 2, None, 2, None, None) == fse.FSE_ERR_INVALID
+    assert lib.fse_schedule_refined(2, 2, None, 4, None, None) == fse.FSE_ERR_INVALID
+    assert lib.fse_schedule_refined(0, 5, None, 4, None, None) == 0
+    assert lib.fse_schedule_refined(-1, 5, None, 4, None, None) == fse.FSE_ERR_INVALID
+    u = np.ones(4, np.int32)
+    w = np.zeros(4, np.int32)
+    assert lib.fse_schedule_refined(2, 2, u.ctypes.data, -1, w.ctypes.data,
+                                    None) == fse.FSE_ERR_INVALID
 
 
 @settings(max_examples=200, deadline=None)
@@ -103,3 +111,33 @@ def test_host_scheduler_large_grid(lib):
     b = oracle.schedule(grid)
     assert a[0] == b[0]
     np.testing.assert_array_equal(a[1], b[1])
+
+
+@settings(max_examples=200, deadline=None)
+@given(st.integers(1, 14), st.integers(1, 14), st.integers(0, 2**31 - 1),
+       st.floats(0.0, 1.0), st.sampled_from([4, 64, 256]))
+def test_host_refined_scheduler_matches_oracle(lib, hb, wb, seed, p, outside):
+    rng = np.random.default_rng(seed)
+    unknown = np.where(rng.random((hb, wb)) < p, rng.integers(1, outside + 1, (hb, wb)),
+                       0).astype(np.int32)
+    a = fse.fse_schedule_refined(unknown, outside)
+    b = oracle.schedule_refined(unknown, outside)
+    assert a[0] == b[0]
+    np.testing.assert_array_equal(a[1], b[1])
+    np.testing.assert_array_equal(a[2], b[2])
+
+
+def test_host_refined_scheduler_large_grid(lib):
+    # 1080p grid, random isolated sample losses plus slices, against the oracle
+    from paper_2207_00233_amd import synth
+    rng = np.random.default_rng(2)
+    lost = synth.slice_loss(rng, 1080, 1920, 16, (0.05, 0.1))
+    lost |= (rng.random((1080, 1920)) < 0.002).astype(np.uint8)
+    pad = np.zeros((68 * 16, 1920), np.uint8)  # 1080 rows = 67.5 block rows
+    pad[:1080] = lost
+    unknown = pad.reshape(68, 16, 120, 16).sum(axis=(1, 3)).astype(np.int32)
+    a = fse.fse_schedule_refined(unknown, 256)
+    b = oracle.schedule_refined(unknown, 256)
+    assert a[0] == b[0] and a[0] > 0
+    np.testing.assert_array_equal(a[1], b[1])
+    np.testing.assert_array_equal(a[2], b[2])
