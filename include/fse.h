@@ -14,7 +14,8 @@
  *   compensation factor gamma), and the model's samples are inserted into the
  *   lost part of the block.  Blocks are processed either in line-scan order
  *   (Section 2) or in waves of mutually non-adjacent blocks chosen by
- *   Algorithm 1 (Section 3, Eq. (3)); the blocks of one wave run concurrently.
+ *   Algorithm 1 (Section 3, Eq. (3)) or by the refined sample-count
+ *   criterion Section 3 suggests; the blocks of one wave run concurrently.
  *
  *   Readings of points the paper leaves open, fixed by this ABI:
  *   - basis phi_k[m,n] = exp(+j 2 pi (k1 m / fft_h + k2 n / fft_w)), L at the
@@ -24,7 +25,8 @@
  *     gamma * P[u] / sum(w); exactly `iterations` iterations;
  *   - neighbours = 8-neighbourhood; rim blocks count their missing
  *     neighbours as not extrapolated (margin +3, corner +5); N_min is the
- *     smallest non-negative count; the wave is filled in raster order;
+ *     smallest non-negative count; the wave is filled in raster order
+ *     (the refined order counts unknown samples instead: FSE_ORDER_REFINED);
  *   - every block of a wave reads the image as it was at the start of the
  *     wave; reconstructed samples are reused unquantized;
  *   - lost output samples are rounded half-to-even and clamped to [0, 255].
