@@ -149,3 +149,40 @@ def test_served_refined_frames_equal_batched():
         np.testing.assert_array_equal(r.out, a.out)
         np.testing.assert_array_equal(r.out_f, a.out_f)
         assert r.waves == a.waves == oracle.schedule_refined(_block_counts(ls), 256)[0]
+
+
+@pytest.mark.parametrize("shape,off", [((70, 90), (5, 11)), ((45, 130), (15, 0))])
+def test_refined_grid_offsets_and_ragged_edges(shape, off):
+    """Blocks partly outside the image (grid shifted, sizes not multiples of
+    16): the counts cover the in-image samples only, outside cells count a
+    whole block; host frames, device frames and the oracle agree (FP64)."""
+    import torch
+    H, W = shape
+    rng = np.random.default_rng(9)
+    img = synth.polygon_image(rng, H, W, radius=(8, 40))
+    lost = np.maximum(synth.hole_loss(rng, H, W, 20),
+                      synth.bernoulli_block_loss(rng, H, W, 16, 0.2))
+    p = fse.Params(border_d=12, iterations=40, precision=fse.FSE_FP64,
+                   order=fse.FSE_ORDER_REFINED, grid_off_x=off[0], grid_off_y=off[1])
+    print(f"[gpu] refined order {shape} offsets {off}", flush=True)
+    with fse.Plan(p) as plan:
+        r = plan.fse_conceal_image([img], [lost], want_float=True)[0]
+    o = oracle.conceal(_oracle_params(p), img, lost)
+    m = lost.astype(bool)
+    assert r.waves == o.waves
+    assert float(np.abs(r.out_f[m] - o.image[m]).max()) <= FP64_TOL
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ti, tl = torch.from_numpy(img).to(dev), torch.from_numpy(lost).to(dev)
+    to = torch.empty_like(ti)
+    tf = torch.empty((H, W), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    pd = fse.Params(border_d=12, iterations=40, precision=fse.FSE_FP64,
+                    order=fse.FSE_ORDER_REFINED, grid_off_x=off[0], grid_off_y=off[1],
+                    flags=fse.FSE_FLAG_DEVICE_PTRS)
+    with fse.Plan(pd, hip_stream=torch.cuda.current_stream().cuda_stream) as plan:
+        plan.conceal_device([{"image": ti.data_ptr(), "lost": tl.data_ptr(), "out": to.data_ptr(),
+                              "out_f64": tf.data_ptr(), "width": W, "height": H}])
+        torch.cuda.synchronize()
+    np.testing.assert_array_equal(to.cpu().numpy(), r.out)
+    np.testing.assert_array_equal(tf.cpu().numpy(), r.out_f)
