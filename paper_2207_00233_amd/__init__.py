@@ -36,6 +36,7 @@ FSE_FP32 = 1
 FSE_FP32_RERANK = 2
 FSE_FP32_F16X3 = 3
 FSE_FLAG_DEVICE_PTRS = 1
+FSE_MAX_ITERATIONS = 1024
 
 EXPORTED = ("fse_plan", "fse_plan_destroy", "fse_conceal_image", "fse_submit",
             "fse_poll", "fse_schedule", "fse_schedule_refined", "fse_last_call_stats",

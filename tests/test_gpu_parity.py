@@ -14,6 +14,7 @@ residual gives exact ties |R[k]| = |R[-k]| whose choice does not change the
 real part of the model.
 """
 import dataclasses
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
@@ -295,6 +296,72 @@ def test_repeated_runs_are_bitwise_identical():
     a = run_gpu(p, [fr.image], [fr.lost])[0]
     b = run_gpu(p, [fr.image], [fr.lost])[0]
     np.testing.assert_array_equal(a.out_f, b.out_f)
+
+
+# ------------------------------------------------------------ maximum sizes
+# The largest area the 64 x 64 basis holds (32 x 32 blocks with d = 16: M =
+# N = 64) and the largest iteration count (FSE_MAX_ITERATIONS): the LDS
+# layouts at their largest (FP64 on 16 wavefronts: 158.8 KB of 160 KB).
+
+def _max_area_frame(seed, H=96, W=128):
+    rng = np.random.default_rng(seed)
+    img = synth.polygon_image(rng, H, W, radius=(10, 50))
+    lost = np.zeros((H, W), np.uint8)
+    lost[5:12, :] = 1          # a strip through the first block row
+    lost[32:64, 32:64] = 1     # a whole 32 x 32 block
+    lost[40:60, 72:90] = 1     # most of another
+    return img, lost
+
+
+def test_maximum_area_and_iterations_fp64():
+    img, lost = _max_area_frame(31)
+    p = fse.Params(block_w=32, block_h=32, border_d=16, iterations=fse.FSE_MAX_ITERATIONS,
+                   precision=fse.FSE_FP64)
+    check_free_running(p, img, lost, FP64_TOL)
+
+
+def test_maximum_area_and_iterations_rerank():
+    img, lost = _max_area_frame(32)
+    p = fse.Params(block_w=32, block_h=32, border_d=16, iterations=fse.FSE_MAX_ITERATIONS,
+                   precision=fse.FSE_FP32_RERANK)
+    r = run_gpu(p, [img], [lost])[0]
+    op = oracle_params(p)
+    grid = np.zeros((3, 4), np.uint8)
+    for b in range(12):
+        grid[b // 4, b % 4] = lost[32 * (b // 4):32 * (b // 4) + 32, 32 * (b % 4):32 * (b % 4) + 32].any()
+    _, wave_of, seq = oracle.schedule(grid)
+    out_f = r.out_f.astype(np.float64)
+    with ThreadPoolExecutor(8) as pool:  # the oracle's C calls release the GIL
+        errs = list(pool.map(lambda b: float(np.abs(np.subtract(*teacher_forced_block(
+            img, lost, out_f, wave_of, op, b // 4, b % 4)[:2])).max()), seq))
+    print(f"[parity] re-rank M = N = 64, K = {p.iterations}: teacher-forced max-abs "
+          f"{max(errs):.3e} over {len(seq)} blocks", flush=True)
+    assert max(errs) <= FP32_TOL
+
+
+def test_maximum_area_f16x3_first_increment():
+    img, lost = _max_area_frame(33)
+    p = fse.Params(block_w=32, block_h=32, border_d=16, iterations=1,
+                   precision=fse.FSE_FP32_F16X3)
+    r = run_gpu(p, [img], [lost], trace=True)[0]
+    op = oracle_params(p)
+    grid = np.zeros((3, 4), np.uint8)
+    for b in range(12):
+        grid[b // 4, b % 4] = lost[32 * (b // 4):32 * (b // 4) + 32, 32 * (b % 4):32 * (b % 4) + 32].any()
+    _, wave_of, _ = oracle.schedule(grid)
+    worst = 0.0
+    for slot, b in enumerate(r.trace_block):
+        _, _, res = teacher_forced_block(img, lost, r.out_f.astype(np.float64), wave_of, op,
+                                         b // 4, b % 4)
+        u_o, dc_o = int(res.u[0]), complex(res.dc[0])
+        u_g, dc_g = int(r.trace_u[slot][0]), complex(r.trace_dc[slot][0])
+        if u_g != u_o:
+            assert u_g == int(mirror(u_o)), (b, u_g, u_o)
+            dc_o = dc_o.conjugate()
+        worst = max(worst, abs(dc_g - dc_o) / abs(dc_o))
+    print(f"[parity] f16x3 M = N = 64 first increment: worst relative error {worst:.3e}",
+          flush=True)
+    assert worst <= F16X3_DC_TOL
 
 
 # ------------------------------------------------------------ full size
