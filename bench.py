@@ -37,6 +37,8 @@ SYNTH_FLOPS = 256 * K_ITER * 4
 FLOPS_PER_BLOCK = ITER_FLOPS + TRANSFORM_FLOPS + SYNTH_FLOPS
 PEAK_FP32_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (non-packed FMA)
 PEAK_FP32_PUBLISHED = 157.3
+SIMDS = 256 * 4            # compute units x SIMDs
+CLOCK_HZ = 2.4e9
 
 
 # sources whose change invalidates a committed traffic measurement: the
@@ -45,11 +47,11 @@ TRAFFIC_SOURCES = ("paper_2207_00233_amd/csrc/fse_kernels.hip", "paper_2207_0023
                    "paper_2207_00233_amd/csrc/fse_runtime.cpp", "paper_2207_00233_amd/csrc/fse_internal.h")
 
 
-def measured_traffic(precision):
-    """HBM bytes of the block kernel over one step (all its launches) from the
-    committed rocprofv3 FETCH_SIZE/WRITE_SIZE measurement, if it was taken on
-    this kernel source, launch configuration (host runtime) and precision;
-    None otherwise."""
+def measured_record(precision):
+    """The committed rocprofv3 counter record of the block kernel over one
+    step (HBM bytes from FETCH_SIZE/WRITE_SIZE, VALU wavefront-instructions
+    from SQ_INSTS_VALU), if it was taken on this kernel source, launch
+    configuration (host runtime) and precision; None otherwise."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "fse_block_kernel_traffic.json")
     try:
@@ -61,7 +63,13 @@ def measured_traffic(precision):
         h.update(open(os.path.join(ROOT, fn), "rb").read())
     if rec.get("precision") != precision or rec.get("kernel_source_sha256") != h.hexdigest():
         return None
-    return rec["traffic_bytes_per_step"]
+    return rec
+
+
+def measured_traffic(precision):
+    """HBM bytes of the block kernel per step (see measured_record), or None."""
+    rec = measured_record(precision)
+    return rec["traffic_bytes_per_step"] if rec else None
 
 
 def log(*a):
@@ -445,6 +453,12 @@ def main():
     busy_ms = head["kernel_busy_ms_per_step"]
     achieved = kflops * lost_blocks / (busy_ms * 1e-3) / 1e12
     traffic = measured_traffic(args.precision)
+    # VALU issue: the committed SQ_INSTS_VALU count of a step over the
+    # kernel's busy time, against what 1024 SIMDs issue (a wave64 VALU
+    # instruction occupies a 16-lane SIMD for 4 cycles)
+    rec = measured_record(args.precision)
+    valu = rec.get("valu_wave_insts_per_step") if rec else None
+    valu_issue_frac = (valu / (busy_ms * 1e-3) / (SIMDS * CLOCK_HZ / 4.0)) if valu else None
 
     fp64 = None
     if not args.no_fp64:
@@ -552,7 +566,12 @@ def main():
                                      "rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0 (copy-"
                                      "calibrated), taken on this kernel source and launch "
                                      "configuration; null when either changed since",
-                     "frac_of_published_fp32_peak": achieved / PEAK_FP32_PUBLISHED},
+                     "frac_of_published_fp32_peak": achieved / PEAK_FP32_PUBLISHED,
+                     "valu_issue_frac": valu_issue_frac,
+                     "valu_issue_note": "VALU wavefront-instructions of a step (rocprofv3 "
+                                        "SQ_INSTS_VALU, same source and launch configuration; "
+                                        "null otherwise) x 4 cycles over 1024 SIMDs x 2.4 GHz "
+                                        "x the kernel's busy time"},
         "fp64_plain": fp64,
         "precision_sweep": sweep,
         "p99_frame_latency_ms": serving["p99_frame_latency_ms"] if serving else None,
