@@ -72,6 +72,11 @@ struct fse_plan_s {
   fse::DevBuf work, state, frames_dev, items_dev, u8_img, u8_lost, u8_out, fout, staging,
       trace_u, trace_dc, flags_dev, io_dev;
   fse::HostBuf pin_in, pin_out;  // pinned staging of host frames (inputs, 8-bit outputs)
+  // pinned staging of the lost-block flags (device frames) and of the work
+  // items of a call; ev_flags / ev_items mark their copies done
+  fse::HostBuf pin_flags, pin_items;
+  hipEvent_t ev_flags = nullptr, ev_items = nullptr;
+  bool items_recorded = false;
   fse::HostPool* pool = nullptr;  // host workers (scheduling, host frame copies)
   std::vector<hipEvent_t> events;
   // wavefronts per block by launch size: at most wide_threshold blocks -> 16,

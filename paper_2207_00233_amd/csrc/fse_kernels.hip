@@ -1323,12 +1323,13 @@ __global__ void fse_scatter_kernel(T* work, uint8_t* state, const FrameDesc* fra
   }
 }
 
-// Working image and state map of every frame from its 8-bit input, and
-// (each nullable) the flag of every block that holds a lost sample and the
-// number of lost samples per block (zeroed by the caller).  blockIdx.y = frame.
+// Working image and state map of every frame from its 8-bit input (when
+// `convert`), and (each nullable) the flag of every block that holds a lost
+// sample and the number of lost samples per block (zeroed by the caller).
+// blockIdx.y = frame.
 template <typename T>
 __global__ void fse_init_kernel(const IoDesc* io, T* work, uint8_t* state, uint8_t* flags,
-                                int32_t* counts, int Bh, int Bw, int gox, int goy) {
+                                int32_t* counts, bool convert, int Bh, int Bw, int gox, int goy) {
   const IoDesc d = io[blockIdx.y];
   for (int y = blockIdx.x; y < d.H; y += gridDim.x) {  // rows; lanes along the row
     const uint8_t* lr = d.lost + (int64_t)y * d.lstride;
@@ -1337,8 +1338,10 @@ __global__ void fse_init_kernel(const IoDesc* io, T* work, uint8_t* state, uint8
     const int64_t frow = d.flag_off + (int64_t)((y + goy) / Bh) * d.wb;
     for (int x = threadIdx.x; x < d.W; x += blockDim.x) {
       const bool l = lr[x] != 0;
-      work[o + x] = l ? T(0) : (T)ir[x];
-      state[o + x] = l ? kPending : kKnown;
+      if (convert) {
+        work[o + x] = l ? T(0) : (T)ir[x];
+        state[o + x] = l ? kPending : kKnown;
+      }
       if (l && flags) flags[frow + (x + gox) / Bw] = 1;
       if (l && counts) atomicAdd(counts + frow + (x + gox) / Bw, 1);
     }
@@ -1469,10 +1472,10 @@ static int grid_rows(int64_t max_pixels) {
 
 template <typename T>
 hipError_t launch_init(const IoDesc* io, int nframes, int64_t max_pixels, T* work,
-                       uint8_t* state, uint8_t* flags, int32_t* counts, int Bh, int Bw,
-                       int gox, int goy, hipStream_t s) {
+                       uint8_t* state, uint8_t* flags, int32_t* counts, bool convert, int Bh,
+                       int Bw, int gox, int goy, hipStream_t s) {
   hipLaunchKernelGGL(fse_init_kernel<T>, dim3(grid_rows(max_pixels), nframes), dim3(256), 0, s,
-                     io, work, state, flags, counts, Bh, Bw, gox, goy);
+                     io, work, state, flags, counts, convert, Bh, Bw, gox, goy);
   return hipGetLastError();
 }
 
@@ -1489,9 +1492,9 @@ template hipError_t launch_scatter<float>(float*, uint8_t*, const FrameDesc*, co
 template hipError_t launch_scatter<double>(double*, uint8_t*, const FrameDesc*, const int32_t*,
                                            int, const double*, int, int, int, int, hipStream_t);
 template hipError_t launch_init<float>(const IoDesc*, int, int64_t, float*, uint8_t*, uint8_t*,
-                                       int32_t*, int, int, int, int, hipStream_t);
+                                       int32_t*, bool, int, int, int, int, hipStream_t);
 template hipError_t launch_init<double>(const IoDesc*, int, int64_t, double*, uint8_t*, uint8_t*,
-                                        int32_t*, int, int, int, int, hipStream_t);
+                                        int32_t*, bool, int, int, int, int, hipStream_t);
 template hipError_t launch_finalize<float>(const IoDesc*, int, int64_t, const uint8_t*,
                                            const float*, hipStream_t);
 template hipError_t launch_finalize<double>(const IoDesc*, int, int64_t, const uint8_t*,

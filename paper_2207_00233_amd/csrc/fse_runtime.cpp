@@ -37,8 +37,8 @@ hipError_t launch_scatter(T* work, uint8_t* state, const FrameDesc* frames, cons
                           hipStream_t s);
 template <typename T>
 hipError_t launch_init(const IoDesc* io, int nframes, int64_t max_pixels, T* work,
-                       uint8_t* state, uint8_t* flags, int32_t* counts, int Bh, int Bw,
-                       int gox, int goy, hipStream_t s);
+                       uint8_t* state, uint8_t* flags, int32_t* counts, bool convert, int Bh,
+                       int Bw, int gox, int goy, hipStream_t s);
 template <typename T>
 hipError_t launch_finalize(const IoDesc* io, int nframes, int64_t max_pixels,
                            const uint8_t* state, const T* work, hipStream_t s);
@@ -401,34 +401,34 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
     }
   }
   if ((rc = chk(hipMemcpyAsync(pl->io_dev.ptr, io.data(), n * sizeof(IoDesc),
-                               hipMemcpyHostToDevice, s))) ||
-      (dev && (rc = chk(hipMemsetAsync(pl->flags_dev.ptr, 0, flag_total * (refined ? 4 : 1),
-                                       s)))) ||
-      (rc = chk(launch_init<T>((const IoDesc*)pl->io_dev.ptr, n, max_pixels, work, state,
-                               dev && !refined ? (uint8_t*)pl->flags_dev.ptr : nullptr,
-                               dev && refined ? (int32_t*)pl->flags_dev.ptr : nullptr, Bh, Bw,
-                               gox, goy, s))))
+                               hipMemcpyHostToDevice, s))))
     return rc;
-  // device frames: the init launch marks the lost blocks (or counts their
-  // lost samples); host frames have them already
-  std::vector<uint8_t> allflags;
-  std::vector<int32_t> allcounts;
+  // device frames: a first pass over the masks marks the lost blocks (or
+  // counts their lost samples) and they are copied back, so that the host
+  // schedules while the second pass converts the images; host frames have
+  // their flags already
+  const size_t flag_bytes = (size_t)flag_total * (refined ? 4 : 1);
+  const IoDesc* iod = (const IoDesc*)pl->io_dev.ptr;
   if (dev) {
-    void* dst = nullptr;
-    if (refined) {
-      allcounts.resize(flag_total);
-      dst = allcounts.data();
-    } else {
-      allflags.resize(flag_total);
-      dst = allflags.data();
-    }
-    if ((rc = chk(hipMemcpyAsync(dst, pl->flags_dev.ptr, flag_total * (refined ? 4 : 1),
+    if ((rc = pl->pin_flags.reserve(std::max<size_t>(1, flag_bytes)))) return rc;
+    if (!pl->ev_flags && hipEventCreateWithFlags(&pl->ev_flags, hipEventDisableTiming) != hipSuccess)
+      return FSE_ERR_DEVICE;
+    if ((rc = chk(hipMemsetAsync(pl->flags_dev.ptr, 0, flag_bytes, s))) ||
+        (rc = chk(launch_init<T>(iod, n, max_pixels, work, state,
+                                 refined ? nullptr : (uint8_t*)pl->flags_dev.ptr,
+                                 refined ? (int32_t*)pl->flags_dev.ptr : nullptr, false, Bh, Bw,
+                                 gox, goy, s))) ||
+        (rc = chk(hipMemcpyAsync(pl->pin_flags.ptr, pl->flags_dev.ptr, flag_bytes,
                                  hipMemcpyDeviceToHost, s))) ||
-        (rc = chk(hipStreamSynchronize(s))))
+        (rc = chk(hipEventRecord(pl->ev_flags, s))))
       return rc;
   }
-  const uint8_t* flag_base = dev ? allflags.data() : host_flags.data();
-  const int32_t* count_base = dev ? allcounts.data() : host_counts.data();
+  if ((rc = chk(launch_init<T>(iod, n, max_pixels, work, state, nullptr, nullptr, true, Bh, Bw,
+                               gox, goy, s))))
+    return rc;
+  if (dev && (rc = chk(hipEventSynchronize(pl->ev_flags)))) return rc;
+  const uint8_t* flag_base = dev ? (const uint8_t*)pl->pin_flags.ptr : host_flags.data();
+  const int32_t* count_base = dev ? (const int32_t*)pl->pin_flags.ptr : host_counts.data();
 
   // processing order per frame
   std::vector<std::vector<int32_t>> wave_of(n), seq(n);
@@ -553,10 +553,20 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
   if (want_trace && ((rc = pl->trace_u.reserve(std::max<int64_t>(1, n_items) * K * sizeof(int32_t))) ||
                      (rc = pl->trace_dc.reserve(std::max<int64_t>(1, n_items) * K * 2 * sizeof(T)))))
     return rc;
-  if (n_items > 0 &&
-      (rc = chk(hipMemcpyAsync(pl->items_dev.ptr, items.data(), items.size() * sizeof(int32_t),
-                               hipMemcpyHostToDevice, s))))
-    return rc;
+  if (n_items > 0) {
+    // through pinned staging, so that the copy does not hold the host; the
+    // previous call's copy out of the staging is done first
+    if (!pl->ev_items && hipEventCreateWithFlags(&pl->ev_items, hipEventDisableTiming) != hipSuccess)
+      return FSE_ERR_DEVICE;
+    if (pl->items_recorded && (rc = chk(hipEventSynchronize(pl->ev_items)))) return rc;
+    if ((rc = pl->pin_items.reserve(items.size() * sizeof(int32_t)))) return rc;
+    std::memcpy(pl->pin_items.ptr, items.data(), items.size() * sizeof(int32_t));
+    if ((rc = chk(hipMemcpyAsync(pl->items_dev.ptr, pl->pin_items.ptr,
+                                 items.size() * sizeof(int32_t), hipMemcpyHostToDevice, s))) ||
+        (rc = chk(hipEventRecord(pl->ev_items, s))))
+      return rc;
+    pl->items_recorded = true;
+  }
   if ((rc = chk(hipMemcpyAsync(pl->frames_dev.ptr, fd.data(), n * sizeof(FrameDesc),
                                hipMemcpyHostToDevice, s))))
     return rc;
@@ -860,6 +870,10 @@ int32_t fse_plan_destroy(fse_plan_t pl) {
   for (DevBuf* b : bufs) b->release();
   pl->pin_in.release();
   pl->pin_out.release();
+  pl->pin_flags.release();
+  pl->pin_items.release();
+  if (pl->ev_flags) (void)hipEventDestroy(pl->ev_flags);
+  if (pl->ev_items) (void)hipEventDestroy(pl->ev_items);
   delete pl->pool;
   pl->pool = nullptr;
   if (pl->own_stream && pl->stream) (void)hipStreamDestroy(pl->stream);

@@ -47,8 +47,8 @@ hipError_t launch_scatter(T* work, uint8_t* state, const FrameDesc* frames, cons
                           hipStream_t s);
 template <typename T>
 hipError_t launch_init(const IoDesc* io, int nframes, int64_t max_pixels, T* work,
-                       uint8_t* state, uint8_t* flags, int32_t* counts, int Bh, int Bw,
-                       int gox, int goy, hipStream_t s);
+                       uint8_t* state, uint8_t* flags, int32_t* counts, bool convert, int Bh,
+                       int Bw, int gox, int goy, hipStream_t s);
 template <typename T>
 hipError_t launch_finalize(const IoDesc* io, int nframes, int64_t max_pixels,
                            const uint8_t* state, const T* work, hipStream_t s);
@@ -263,7 +263,7 @@ static int worker_admit(Serving* sv, const std::shared_ptr<Req>& r) {
                      hipMemcpyHostToDevice, s) != hipSuccess)
     return FSE_ERR_DEVICE;
   if (launch_init<T>((const IoDesc*)sv->d_io.ptr + r->slot, 1, px, work, state, nullptr, nullptr,
-                     pl->p.block_h, pl->p.block_w, pl->p.grid_off_x, pl->p.grid_off_y,
+                     true, pl->p.block_h, pl->p.block_w, pl->p.grid_off_x, pl->p.grid_off_y,
                      s) != hipSuccess)
     return FSE_ERR_DEVICE;
   return FSE_OK;
