@@ -316,87 +316,112 @@ done:
 /* ------------------------------------------------------------------------ */
 
 /*
+ * The two orders of Section 3 share one loop, written from the section's
+ * description rather than from Algorithm 1's incremental bookkeeping: before
+ * every wave the count N(b) of each pending block is recomputed from its
+ * definition, the smallest non-negative count is taken, the pending blocks
+ * with that count are scanned in raster order and a block joins the wave
+ * unless one of its 8 neighbours has already joined; the blocks of the wave
+ * are then marked extrapolated.
+ *
+ * weight[b] is what a pending neighbour b contributes to a count, `outside`
+ * what a neighbour position outside the image contributes.  Algorithm 1:
+ * weight 1 for a block with lost samples and outside = 1 (a missing
+ * neighbour counts as not extrapolated, which is the +3 margin and +5 corner
+ * rule).  Refined order: weight = the block's lost samples and outside = a
+ * whole block's samples.
+ */
+static long neighbour_count(int hb, int wb, const long *weight, const uint8_t *pending,
+                            long outside, int i, int j) {
+  long n = 0;
+  for (int di = -1; di <= 1; ++di)
+    for (int dj = -1; dj <= 1; ++dj) {
+      if (!di && !dj) continue;
+      int y = i + di, x = j + dj;
+      if (y < 0 || y >= hb || x < 0 || x >= wb)
+        n += outside;
+      else if (pending[y * wb + x])
+        n += weight[y * wb + x];
+    }
+  return n;
+}
+
+static int waves_by_count(int hb, int wb, const long *weight, long outside,
+                          int32_t *wave_of, int32_t *order_out) {
+  int nb = hb * wb, nwaves = 0, pos = 0;
+  uint8_t *pending = (uint8_t *)malloc((size_t)nb);
+  uint8_t *in_s = (uint8_t *)malloc((size_t)nb);
+  long *cnt = (long *)malloc(sizeof(long) * nb);
+  for (int b = 0; b < nb; ++b) {
+    wave_of[b] = -1;
+    pending[b] = weight[b] > 0;
+  }
+  for (;;) {
+    long nmin = -1;
+    for (int i = 0; i < hb; ++i)
+      for (int j = 0; j < wb; ++j) {
+        int b = i * wb + j;
+        if (!pending[b]) continue;
+        cnt[b] = neighbour_count(hb, wb, weight, pending, outside, i, j);
+        if (nmin < 0 || cnt[b] < nmin) nmin = cnt[b];
+      }
+    if (nmin < 0) break;  /* nothing left to extrapolate */
+    memset(in_s, 0, (size_t)nb);
+    for (int i = 0; i < hb; ++i)
+      for (int j = 0; j < wb; ++j) {
+        int b = i * wb + j;
+        if (!pending[b] || cnt[b] != nmin) continue;
+        int touches = 0;
+        for (int di = -1; di <= 1; ++di)
+          for (int dj = -1; dj <= 1; ++dj) {
+            int y = i + di, x = j + dj;
+            if ((di || dj) && y >= 0 && y < hb && x >= 0 && x < wb && in_s[y * wb + x])
+              touches = 1;
+          }
+        if (touches) continue;
+        in_s[b] = 1;
+        wave_of[b] = nwaves;
+        if (order_out) order_out[pos] = b;
+        ++pos;
+      }
+    for (int b = 0; b < nb; ++b)
+      if (in_s[b]) pending[b] = 0;
+    ++nwaves;
+  }
+  free(pending);
+  free(in_s);
+  free(cnt);
+  return nwaves;
+}
+
+/*
  * lost[hb*wb]: nonzero if the block has samples to extrapolate.
  * wave_of[hb*wb] (out): wave index of each lost block, -1 for the others.
  * order_out[hb*wb] (out, nullable): lost blocks in processing order (waves in
  * sequence, raster order inside a wave).
+ * order: 1 = line scan (Section 2), otherwise Algorithm 1 (Section 3).
  * Returns the number of waves.
  */
 int oracle_schedule(int hb, int wb, const uint8_t *lost, int order,
                     int32_t *wave_of, int32_t *order_out) {
   if (hb <= 0 || wb <= 0) return 0;
-  int nb = hb * wb, nwaves = 0, pos = 0;
-  for (int b = 0; b < nb; ++b) wave_of[b] = -1;
+  int nb = hb * wb;
   if (order == 1) {
-    for (int b = 0; b < nb; ++b)
+    int nwaves = 0, pos = 0;
+    for (int b = 0; b < nb; ++b) {
+      wave_of[b] = -1;
       if (lost[b]) {
         wave_of[b] = nwaves++;
         if (order_out) order_out[pos++] = b;
       }
+    }
     return nwaves;
   }
-  int *cnt = (int *)calloc((size_t)nb, sizeof(int));
-  uint8_t *in_s = (uint8_t *)calloc((size_t)nb, 1);
-  /* Initialization, first pass: every block with losses adds 1 to each
-   * neighbour; rim blocks add the number of neighbours they lack. */
-  for (int i = 0; i < hb; ++i)
-    for (int j = 0; j < wb; ++j) {
-      int inside = 0;
-      for (int di = -1; di <= 1; ++di)
-        for (int dj = -1; dj <= 1; ++dj) {
-          if (!di && !dj) continue;
-          int y = i + di, x = j + dj;
-          if (y < 0 || y >= hb || x < 0 || x >= wb) continue;
-          ++inside;
-          if (lost[i * wb + j]) cnt[y * wb + x] += 1;
-        }
-      cnt[i * wb + j] += 8 - inside;
-    }
-  /* second pass: blocks without losses are finished */
-  for (int b = 0; b < nb; ++b)
-    if (!lost[b]) cnt[b] = -1;
-  for (;;) {
-    int nmin = -1;
-    for (int b = 0; b < nb; ++b)
-      if (cnt[b] >= 0 && (nmin < 0 || cnt[b] < nmin)) nmin = cnt[b];
-    if (nmin < 0) break;
-    memset(in_s, 0, (size_t)nb);
-    for (int i = 0; i < hb; ++i)
-      for (int j = 0; j < wb; ++j) {
-        if (cnt[i * wb + j] != nmin) continue;
-        int clash = 0;
-        for (int di = -1; di <= 1 && !clash; ++di)
-          for (int dj = -1; dj <= 1; ++dj) {
-            if (!di && !dj) continue;
-            int y = i + di, x = j + dj;
-            if (y < 0 || y >= hb || x < 0 || x >= wb) continue;
-            if (in_s[y * wb + x]) { clash = 1; break; }
-          }
-        if (clash) continue;
-        in_s[i * wb + j] = 1;
-        wave_of[i * wb + j] = nwaves;
-        if (order_out) order_out[pos] = i * wb + j;
-        ++pos;
-      }
-    /* after the wave: the block is done, its neighbours lose one pending
-     * neighbour */
-    for (int b = 0; b < nb; ++b) {
-      if (!in_s[b]) continue;
-      int i = b / wb, j = b % wb;
-      cnt[b] = -1;
-      for (int di = -1; di <= 1; ++di)
-        for (int dj = -1; dj <= 1; ++dj) {
-          if (!di && !dj) continue;
-          int y = i + di, x = j + dj;
-          if (y < 0 || y >= hb || x < 0 || x >= wb) continue;
-          if (cnt[y * wb + x] >= 0) cnt[y * wb + x] -= 1;
-        }
-    }
-    ++nwaves;
-  }
-  free(cnt);
-  free(in_s);
-  return nwaves;
+  long *weight = (long *)malloc(sizeof(long) * nb);
+  for (int b = 0; b < nb; ++b) weight[b] = lost[b] ? 1 : 0;
+  int nw = waves_by_count(hb, wb, weight, 1, wave_of, order_out);
+  free(weight);
+  return nw;
 }
 
 /*
@@ -408,73 +433,12 @@ int oracle_schedule(int hb, int wb, const uint8_t *lost, int order,
 int oracle_schedule_refined(int hb, int wb, const int32_t *unknown, int outside,
                             int32_t *wave_of, int32_t *order_out) {
   if (hb <= 0 || wb <= 0) return 0;
-  int nb = hb * wb, nwaves = 0, pos = 0;
-  long *cnt = (long *)calloc((size_t)nb, sizeof(long));
-  int32_t *left = (int32_t *)malloc(sizeof(int32_t) * nb);  /* samples still unknown */
-  uint8_t *in_s = (uint8_t *)calloc((size_t)nb, 1);
-  for (int b = 0; b < nb; ++b) {
-    wave_of[b] = -1;
-    left[b] = unknown[b];
-  }
-  /* initial N: unknown samples of the 8 neighbours, outside cells whole */
-  for (int i = 0; i < hb; ++i)
-    for (int j = 0; j < wb; ++j) {
-      long n = 0;
-      for (int di = -1; di <= 1; ++di)
-        for (int dj = -1; dj <= 1; ++dj) {
-          if (!di && !dj) continue;
-          int y = i + di, x = j + dj;
-          if (y < 0 || y >= hb || x < 0 || x >= wb)
-            n += outside;
-          else
-            n += left[y * wb + x];
-        }
-      cnt[i * wb + j] = left[i * wb + j] > 0 ? n : -1;
-    }
-  for (;;) {
-    long nmin = -1;
-    for (int b = 0; b < nb; ++b)
-      if (cnt[b] >= 0 && (nmin < 0 || cnt[b] < nmin)) nmin = cnt[b];
-    if (nmin < 0) break;
-    memset(in_s, 0, (size_t)nb);
-    for (int i = 0; i < hb; ++i)
-      for (int j = 0; j < wb; ++j) {
-        if (cnt[i * wb + j] != nmin) continue;
-        int clash = 0;
-        for (int di = -1; di <= 1 && !clash; ++di)
-          for (int dj = -1; dj <= 1; ++dj) {
-            if (!di && !dj) continue;
-            int y = i + di, x = j + dj;
-            if (y < 0 || y >= hb || x < 0 || x >= wb) continue;
-            if (in_s[y * wb + x]) { clash = 1; break; }
-          }
-        if (clash) continue;
-        in_s[i * wb + j] = 1;
-        wave_of[i * wb + j] = nwaves;
-        if (order_out) order_out[pos] = i * wb + j;
-        ++pos;
-      }
-    /* after the wave: the block's samples are known; each pending neighbour
-     * has that many unknown samples fewer around it */
-    for (int b = 0; b < nb; ++b) {
-      if (!in_s[b]) continue;
-      int i = b / wb, j = b % wb;
-      cnt[b] = -1;
-      for (int di = -1; di <= 1; ++di)
-        for (int dj = -1; dj <= 1; ++dj) {
-          if (!di && !dj) continue;
-          int y = i + di, x = j + dj;
-          if (y < 0 || y >= hb || x < 0 || x >= wb) continue;
-          if (cnt[y * wb + x] >= 0) cnt[y * wb + x] -= left[b];
-        }
-      left[b] = 0;
-    }
-    ++nwaves;
-  }
-  free(cnt);
-  free(left);
-  free(in_s);
-  return nwaves;
+  int nb = hb * wb;
+  long *weight = (long *)malloc(sizeof(long) * nb);
+  for (int b = 0; b < nb; ++b) weight[b] = unknown[b] > 0 ? unknown[b] : 0;
+  int nw = waves_by_count(hb, wb, weight, outside, wave_of, order_out);
+  free(weight);
+  return nw;
 }
 
 /* ------------------------------------------------------------------------ */
