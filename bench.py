@@ -36,7 +36,13 @@ TRANSFORM_FLOPS = 2 * 2.5 * 4096 * 12
 SYNTH_FLOPS = 256 * K_ITER * 4
 FLOPS_PER_BLOCK = ITER_FLOPS + TRANSFORM_FLOPS + SYNTH_FLOPS
 PEAK_FP32_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (non-packed FMA)
-PEAK_FP32_PUBLISHED = 157.3
+PEAK_FP32_PUBLISHED = 157.3  # MI355X's published FP32 vector peak (packed FP32)
+# The method's own HBM bytes per lost block: the 44 x 44 area read (float
+# sample + state byte) and the 16 x 16 block written back (float + state).
+ALG_HBM_BYTES_PER_BLOCK = (BLOCK + 2 * BORDER) ** 2 * 5 + BLOCK * BLOCK * 5
+# whether a precision mode meets the parity bar (0.5 max-abs on every block,
+# teacher-forced; tests/test_gpu_precision_sweep.py)
+MEETS_BAR = {"fp64": True, "fp32_rerank": True, "fp32": False, "fp32_f16x3": False}
 SIMDS = 256 * 4            # compute units x SIMDs
 CLOCK_HZ = 2.4e9
 
@@ -269,21 +275,24 @@ def end_to_end(fse, frames, precision, steps=2):
             "form": "host uint8 frames in, host uint8 frames out, one call per step"}
 
 
-def serving_run(fse, synth, duration_s=3.0, warmup_s=0.5, rate_hz=240.0, seed=0):
+def serving_run(fse, synth, duration_s=10.0, warmup_s=1.0, rate_hz=240.0, seed=0,
+                precision=None):
     """Poisson stream of drifting-texture frames (30 % 1280x720, 50 % 1920x1080,
-    20 % 3840x2160, 2-15 % slice losses) submitted in real time; frames are
-    drawn from a pre-generated pool so that generation does not pace the
-    stream.  Latency is the library's submit -> result-on-host time."""
+    20 % 3840x2160, 2-15 % slice losses) submitted in real time for
+    warmup_s + duration_s seconds; the frames are drawn from a pre-generated
+    pool (12 drifting frames per resolution, 6 at 2160p, each arrival pairing
+    one of them with one of 16 loss masks) so that generation does not pace
+    the stream.  Latency is the library's submit -> result-on-host time."""
     import threading
     rng = np.random.default_rng(seed)
     scene = int(rng.integers(0, 2**31 - 1))
     pool = {}
     for (w, h), _ in synth.SERVING_MIX:
-        n = 2 if w >= 3840 else 4
-        pool[(w, h)] = []
-        for i in range(n):
-            img = synth.drifting_frame(np.random.default_rng(scene), h, w, i / rate_hz, rng)
-            pool[(w, h)].append((img, synth.slice_loss(rng, h, w, BLOCK, (0.02, 0.15))))
+        n = 6 if w >= 3840 else 12
+        imgs = [synth.drifting_frame(np.random.default_rng(scene), h, w, i / rate_hz, rng)
+                for i in range(n)]
+        masks = [synth.slice_loss(rng, h, w, BLOCK, (0.02, 0.15)) for _ in range(16)]
+        pool[(w, h)] = (imgs, masks)
     sizes = [m[0] for m in synth.SERVING_MIX]
     probs = np.array([m[1] for m in synth.SERVING_MIX])
     total_s = warmup_s + duration_s
@@ -292,9 +301,11 @@ def serving_run(fse, synth, duration_s=3.0, warmup_s=0.5, rate_hz=240.0, seed=0)
         t += rng.exponential(1.0 / rate_hz)
         if t >= total_s:
             break
-        key = sizes[int(rng.choice(len(sizes), p=probs))]
-        arrivals.append((t, pool[key][len(arrivals) % len(pool[key])]))
-    p = fse.Params(border_d=BORDER, iterations=K_ITER, precision=fse.FSE_FP32,
+        imgs, masks = pool[sizes[int(rng.choice(len(sizes), p=probs))]]
+        arrivals.append((t, (imgs[int(rng.integers(len(imgs)))],
+                             masks[int(rng.integers(len(masks)))])))
+    p = fse.Params(border_d=BORDER, iterations=K_ITER,
+                   precision=fse.FSE_FP32_RERANK if precision is None else precision,
                    device_mem_budget=16 << 30, max_inflight_frames=256)
     plan = fse.Plan(p)
     tickets = []
@@ -338,7 +349,9 @@ def serving_run(fse, synth, duration_s=3.0, warmup_s=0.5, rate_hz=240.0, seed=0)
             "max_frame_latency_ms": float(lat.max()),
             "sustained_lost_blocks_per_s": done_blocks / (t_end - warmup_s),
             "offered_lost_blocks_per_s": done_blocks / duration_s,
-            "mix": "30% 1280x720, 50% 1920x1080, 20% 3840x2160; 2-15% slice losses; FP32; K=200"}
+            "precision": {fse.FSE_FP32: "fp32", fse.FSE_FP32_RERANK: "fp32_rerank",
+                          fse.FSE_FP64: "fp64", fse.FSE_FP32_F16X3: "fp32_f16x3"}[p.precision],
+            "mix": "30% 1280x720, 50% 1920x1080, 20% 3840x2160; 2-15% slice losses; K=200"}
 
 
 def main():
@@ -395,6 +408,9 @@ def main():
               "width": i.shape[1], "height": i.shape[0]} for i, l, o in zip(imgs, losts, outs)]
     stream = torch.cuda.current_stream().cuda_stream
 
+    names = {fse.FSE_FP32: "fp32", fse.FSE_FP32_RERANK: "fp32_rerank", fse.FSE_FP64: "fp64",
+             fse.FSE_FP32_F16X3: "fp32_f16x3"}
+
     def batched(precision, steps, warmup):
         p = fse.Params(border_d=BORDER, iterations=K_ITER, precision=precision,
                        flags=fse.FSE_FLAG_DEVICE_PTRS)
@@ -402,7 +418,7 @@ def main():
         for _ in range(warmup):
             plan.conceal_device(descs)
         torch.cuda.synchronize()
-        kms, tms, busy, launches, blocks = 0.0, 0.0, 0.0, 0, 0
+        kms, tms, busy, launches, blocks, rescored = 0.0, 0.0, 0.0, 0, 0, 0
         t0 = time.perf_counter()
         for _ in range(steps):
             plan.conceal_device(descs)
@@ -412,18 +428,19 @@ def main():
             busy += cs["busy_ms"]
             launches += cs["launches"]
             blocks += cs["blocks"]
+            rescored += cs["rescored"]
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         plan.close()
         return {"value": blocks / dt, "ms_per_step": dt / steps * 1e3,
+                "meets_parity_bar": MEETS_BAR[names[precision]],
+                "rescored_iterations_per_step": rescored // steps,
                 "kernel_ms_per_step": kms / steps, "transform_ms_per_step": tms / steps,
                 "kernel_busy_ms_per_step": busy / steps, "groups": cs["groups"],
                 "launches_per_step": launches // steps,
                 "blocks_per_step": blocks // steps, "avg_launch_ms": kms / max(1, launches),
                 "blocks_per_launch": blocks / max(1, launches)}
 
-    names = {fse.FSE_FP32: "fp32", fse.FSE_FP32_RERANK: "fp32_rerank", fse.FSE_FP64: "fp64",
-             fse.FSE_FP32_F16X3: "fp32_f16x3"}
     head_prec = {"fp32": fse.FSE_FP32, "fp32_rerank": fse.FSE_FP32_RERANK,
                  "fp32_f16x3": fse.FSE_FP32_F16X3}[args.precision]
     log(f"[bench] batched {args.precision}: {args.steps} timed steps")
@@ -553,8 +570,17 @@ def main():
                    "lost_blocks_per_step": lost_blocks, "frames": len(frames),
                    "launches_per_step": launches // args.steps,
                    "hip_hw_queues": int(os.environ["GPU_MAX_HW_QUEUES"])},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_PUBLISHED,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_PUBLISHED, "traffic": traffic,
+                     "peak_nonpacked": PEAK_FP32_TFLOPS,
+                     "frac_nonpacked": achieved / PEAK_FP32_TFLOPS,
+                     "peak_note": "published FP32 vector peak (counts packed FP32); this "
+                                  "build compiles without packed FP32 instructions, so "
+                                  "78.6 TFLOP/s (256 CU x 4 SIMD x 16 lanes x FMA x "
+                                  "2.4 GHz) is what it can issue",
+                     "algorithmic_hbm_bytes_per_step": ALG_HBM_BYTES_PER_BLOCK * lost_blocks,
+                     "traffic_over_algorithmic": (traffic / (ALG_HBM_BYTES_PER_BLOCK * lost_blocks)
+                                                  if traffic else None),
                      "kernel": "fse_block_kernel<float>",
                      "avg_launch_ms": avg_launch_ms, "blocks_per_launch": blocks_per_launch,
                      "kernel_busy_ms_per_step": busy_ms, "groups": head["groups"],
@@ -566,7 +592,6 @@ def main():
                                      "rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0 (copy-"
                                      "calibrated), taken on this kernel source and launch "
                                      "configuration; null when either changed since",
-                     "frac_of_published_fp32_peak": achieved / PEAK_FP32_PUBLISHED,
                      "valu_issue_frac": valu_issue_frac,
                      "valu_issue_note": "VALU wavefront-instructions of a step (rocprofv3 "
                                         "SQ_INSTS_VALU, same source and launch configuration; "

@@ -66,14 +66,24 @@ typedef struct fse_plan_s *fse_plan_t; /* opaque, owned by the library */
  * losses it orders by sample counts, usually in more, smaller waves. */
 enum { FSE_ORDER_OPTIMIZED = 0, FSE_ORDER_LINESCAN = 1, FSE_ORDER_REFINED = 2 };
 
-/* Arithmetic of the per-block iteration. */
+/* Arithmetic of the per-block iteration.  Only FSE_FP64 and FSE_FP32_RERANK
+ * reproduce the FP64 selection closely enough for a maximum sample error of
+ * 0.5 on the 8-bit scale in every block; FSE_FP32 and FSE_FP32_F16X3 compute
+ * their spectra in float, whose rounding (about 1e-7 of the largest spectrum
+ * entry) decides a few near-tied selections differently (measured: a few
+ * blocks in a hundred above 0.5, whole-image PSNR within 0.02 dB). */
 enum {
   FSE_FP64 = 0,        /* spectra, weights, coefficients in double */
   FSE_FP32 = 1,        /* spectra and iteration in float; synthesis sums in double */
   FSE_FP32_RERANK = 2, /* transforms in double, iteration in float; whenever another
                           spectrum entry comes within rerank_gap (relative) of the
-                          selected maximum of |R|^2, the candidates are re-scored
-                          exactly in double (R0 - sum dc_i W[k - u_i]) */
+                          float maximum of |R|^2, every entry within that gap is
+                          re-scored exactly in double (R0 - sum dc_i W[k - u_i], with
+                          the increments dc_i as applied) and the largest exact value
+                          is selected, ties to the smallest index; no candidate is
+                          dropped (fse_call_stats counts them).  The float spectrum
+                          is not re-scored once its maximum falls below 2^-40 of the
+                          block's first maximum (rounding noise) */
   FSE_FP32_F16X3 = 3    /* iteration as FSE_FP32; both DFT stages as dense products
                           on matrix cores, every operand split into two f16 parts
                           (about 22 significant bits; three products each, float
@@ -236,7 +246,15 @@ int32_t fse_schedule_refined(int32_t hb, int32_t wb, const int32_t *unknown, int
  *                extrapolation launch (all groups);
  *   groups       number of frame groups;
  *   busy_ms      device time during which at least one launch of the
- *                iteration kernel ran (union of the launch intervals). */
+ *                iteration kernel ran (union of the launch intervals);
+ * FSE_FP32_RERANK, over all blocks of the call (0 in the other modes):
+ *   rescored            iterations whose selection was re-scored exactly;
+ *   rescore_candidates  entries re-scored (summed over wavefronts);
+ *   rescore_wide        wavefront re-scores that took several rounds of
+ *                       candidates (more than 3 with 4 wavefronts per block,
+ *                       more than 2 otherwise);
+ *   rescore_max_wave    most entries one wavefront re-scored in one
+ *                       iteration. */
 typedef struct {
   double kernel_ms;
   int64_t launches;
@@ -246,6 +264,10 @@ typedef struct {
   double span_ms;
   int64_t groups;
   double busy_ms;
+  int64_t rescored;
+  int64_t rescore_candidates;
+  int64_t rescore_wide;
+  int64_t rescore_max_wave;
 } fse_call_stats;
 int32_t fse_last_call_stats(fse_plan_t plan, fse_call_stats *out);
 

@@ -99,7 +99,9 @@ class _CallStats(ctypes.Structure):
     _fields_ = [("kernel_ms", ctypes.c_double), ("launches", ctypes.c_int64),
                 ("blocks", ctypes.c_int64), ("total_ms", ctypes.c_double),
                 ("transform_ms", ctypes.c_double), ("span_ms", ctypes.c_double),
-                ("groups", ctypes.c_int64), ("busy_ms", ctypes.c_double)]
+                ("groups", ctypes.c_int64), ("busy_ms", ctypes.c_double),
+                ("rescored", ctypes.c_int64), ("rescore_candidates", ctypes.c_int64),
+                ("rescore_wide", ctypes.c_int64), ("rescore_max_wave", ctypes.c_int64)]
 
 
 class _Tuning(ctypes.Structure):
@@ -344,9 +346,7 @@ class Plan:
     def last_call_stats(self) -> dict:
         cs = _CallStats()
         _check(self._lib.fse_last_call_stats(self.handle, ctypes.byref(cs)), "fse_last_call_stats")
-        return {"kernel_ms": cs.kernel_ms, "launches": cs.launches, "blocks": cs.blocks,
-                "total_ms": cs.total_ms, "transform_ms": cs.transform_ms,
-                "span_ms": cs.span_ms, "groups": cs.groups, "busy_ms": cs.busy_ms}
+        return {k: getattr(cs, k) for k, _ in _CallStats._fields_}
 
     # -- fse_plan_get_tuning / fse_plan_set_tuning ------------------------------
     def get_tuning(self) -> dict:

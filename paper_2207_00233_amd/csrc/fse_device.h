@@ -47,7 +47,17 @@ struct BlockArgs {
   double empty_fill;
   double delta64, gamma64; // the same parameters in double (FP64 transforms, re-rank)
   double* spec64;          // FP64 spectra per work item (re-rank mode), see below
-  double rerank_gap;       // relative |R|^2 gap that triggers an FP64 re-rank
+  double rerank_gap;       // relative |R|^2 gap that triggers an exact re-score
+  unsigned long long* counters;  // nullable: re-scoring statistics (kCnt*)
+};
+
+// Re-scoring statistics of a call (BlockArgs::counters, summed over blocks).
+enum : int {
+  kCntRescored = 0,   // iterations whose selection was re-scored exactly
+  kCntCandidates = 1, // candidates re-scored (over all wavefronts)
+  kCntWide = 2,       // wavefront re-scores that took several rounds of candidates
+  kCntMaxWave = 3,    // most candidates one wavefront re-scored in one iteration
+  kCntSlots = 4
 };
 
 // Work item encoding: the first int holds the frame index in its low 24 bits

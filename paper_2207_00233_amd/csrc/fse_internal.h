@@ -69,6 +69,7 @@ struct fse_plan_s {
   std::vector<double> twid;    // 64 x (cos, sin)(2 pi t / 64)
   fse::DevBuf tbl_radial, tbl_twid, tbl_twid64, tbl_radial64;
   fse::DevBuf spec64;          // FP64 spectra of a step (re-rank mode)
+  fse::DevBuf counters;        // re-scoring statistics of a call (kCntSlots x uint64)
   fse::DevBuf work, state, frames_dev, items_dev, u8_img, u8_lost, u8_out, fout, staging,
       trace_u, trace_dc, flags_dev, io_dev;
   fse::HostBuf pin_in, pin_out;  // pinned staging of host frames (inputs, 8-bit outputs)

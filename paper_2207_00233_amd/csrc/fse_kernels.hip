@@ -774,7 +774,7 @@ __global__ __launch_bounds__(256, 3) void fse_dft64_kernel(BlockArgs<float> a,
   const int fw = a.items[2 * item], bij = a.items[2 * item + 1];
   const int fr = fw & kItemFrameMask;
   if (fw >> kItemPrioShift) __builtin_amdgcn_s_setprio(2);
-  const int bi = bij >> 16, bj = bij & 0xffff;
+  const int bi = (int)((unsigned)bij >> 16), bj = bij & 0xffff;
   const FrameDesc fd = a.frames[fr];
   const int by0 = bi * a.Bh - a.goy, bx0 = bj * a.Bw - a.gox;
   const double W0 = gather_area<double, float, WAVES, false>(
@@ -948,7 +948,7 @@ fse_block_kernel(BlockArgs<T> a) {
   // items on the critical chain of waves issue ahead of the other
   // workgroups sharing their SIMDs
   if (fw >> kItemPrioShift) __builtin_amdgcn_s_setprio(2);
-  const int bi = bij >> 16, bj = bij & 0xffff;
+  const int bi = (int)((unsigned)bij >> 16), bj = bij & 0xffff;
   const FrameDesc fd = a.frames[fr];
   const int H = fd.H, W = fd.W;
   T* img = a.work + fd.off;
@@ -956,6 +956,12 @@ fse_block_kernel(BlockArgs<T> a) {
   const int by0 = bi * a.Bh - a.goy, bx0 = bj * a.Bw - a.gox;
 
   load_twiddles<T>(smem, L, a.twid64, !RERANK);
+  // re-scoring statistics of this wavefront (uniform), added to the call's
+  // counters once, after everything else the block does
+  unsigned st_rescored = 0u, st_cand = 0u, st_wide = 0u, st_max = 0u;
+  // re-rank: no exact re-scoring at or below this key (keys up to 63 carry
+  // only row bits: |R|^2 = 0)
+  unsigned floor_u = 63u;
 
   VecR<T, ROWS> rr, ri;
   T wvr[ROWS], wvi[ROWS];
@@ -1103,32 +1109,24 @@ fse_block_kernel(BlockArgs<T> a) {
           const unsigned thr_g = __float_as_uint(__uint_as_float(gk) * (float)(1.0 - a.rerank_gap));
           const int contrib =
               (lane < WAVES && mine.key >= thr_g) ? (mine.k >> 12) : 0;
-          const bool rerank = __ballot(contrib >= 2) != 0ull ||
-                              __builtin_popcountll(__ballot(contrib >= 1)) >= 2;
+          // no re-scoring once the float maximum is rounding noise: at or
+          // below 2^-40 of the block's first maximum (an all-zero spectrum
+          // would otherwise tie every entry)
+          const bool live = gk > floor_u;
+          if (it == 0) floor_u = (gk >> 23) > 40u ? gk - (40u << 23) : 63u;
+          const bool rerank = live && (__ballot(contrib >= 2) != 0ull ||
+                                       __builtin_popcountll(__ballot(contrib >= 1)) >= 2);
           if (rerank) {  // uniform: every wavefront read the same slots
-            // Every wavefront re-scores its own entries within the gap of the
-            // block maximum (at most kCandWave, in row-major order) exactly in
-            // double, and offers its best one; one barrier joins them.
-            constexpr int kCandWave = 3;
-            unsigned long long packed = 0ull;  // 12-bit indices
-            int nc = 0;
-#pragma unroll
-            for (int j = 0; j < ROWS; ++j) {
-              unsigned long long mm = __ballot(key[j] >= thr_g);
-              while (mm && nc < kCandWave) {
-                const int l = __builtin_ctzll(mm);
-                mm &= mm - 1;
-                packed |= (unsigned long long)((row_of<WAVES, SPLIT>(wave, j) << 6) | l)
-                          << (12 * nc);
-                ++nc;
-              }
-            }
-            // exact |R|^2 of the wavefront's NC candidates (NC = nc, uniform):
-            // R0 - sum_i dc_i W[k - u_i] in double; the best one (ties to the
-            // smallest index) goes to (bex, bre, bim, bkx)
+            // Every wavefront re-scores all of its entries within the gap of
+            // the block maximum exactly in double, three at a time (two with
+            // 8 or 16 wavefronts) in row-major order, and offers its best
+            // one; one barrier joins them.  No candidate is dropped.
             double bex = -1.0, bre = 0.0, bim = 0.0;
             int bkx = 1 << 30;
-            auto rescore = [&](auto nc_tag) {
+            // exact |R|^2 of NC candidates (12-bit indices in `packed`):
+            // R0 - sum_i dc_i W[k - u_i] in double; the best one (ties to the
+            // smallest index) goes to (bex, bre, bim, bkx)
+            auto rescore = [&](auto nc_tag, unsigned long long packed) {
               constexpr int NC = decltype(nc_tag)::value;
               int kc[NC];
               double acc[2 * NC], r0r[NC], r0i[NC];
@@ -1182,9 +1180,33 @@ fse_block_kernel(BlockArgs<T> a) {
                 }
               }
             };
-            if (nc == 1) rescore(std::integral_constant<int, 1>());
-            else if (nc == 2) rescore(std::integral_constant<int, 2>());
-            else if (nc == 3) rescore(std::integral_constant<int, 3>());
+            constexpr int kChunk = WAVES == 4 ? 3 : 2;  // register budget
+            unsigned long long packed = 0ull;
+            int nc = 0, ncw = 0;
+#pragma unroll
+            for (int j = 0; j < ROWS; ++j) {
+              unsigned long long mm = __ballot(key[j] >= thr_g);
+              while (mm) {  // uniform
+                const int l = __builtin_ctzll(mm);
+                mm &= mm - 1;
+                packed |= (unsigned long long)((row_of<WAVES, SPLIT>(wave, j) << 6) | l)
+                          << (12 * nc);
+                ++ncw;
+                if (++nc == kChunk) {
+                  rescore(std::integral_constant<int, kChunk>(), packed);
+                  nc = 0;
+                  packed = 0ull;
+                }
+              }
+            }
+            if (nc == 1) rescore(std::integral_constant<int, 1>(), packed);
+            if constexpr (kChunk == 3) {
+              if (nc == 2) rescore(std::integral_constant<int, 2>(), packed);
+            }
+            st_rescored += 1u;
+            st_cand += (unsigned)ncw;
+            st_wide += ncw > kChunk ? 1u : 0u;
+            st_max = max(st_max, (unsigned)ncw);
             Slot* ex = reinterpret_cast<Slot*>(smem + L.cand) + (it & 1) * WAVES;
             if (lane == 0) {
               Slot v;
@@ -1299,6 +1321,14 @@ fse_block_kernel(BlockArgs<T> a) {
       a.trace_dc[((int64_t)item * K + i) * 2 + 1] = empty ? T(0) : hdc[2 * i + 1];
     }
   }
+  if (RERANK && a.counters && lane == 0 && st_rescored > 0u) {
+    // one update per wavefront and block (re-scored iterations counted once,
+    // by wavefront 0); nothing waits for these atomics
+    if (wave == 0) atomicAdd(&a.counters[kCntRescored], (unsigned long long)st_rescored);
+    if (st_cand) atomicAdd(&a.counters[kCntCandidates], (unsigned long long)st_cand);
+    if (st_wide) atomicAdd(&a.counters[kCntWide], (unsigned long long)st_wide);
+    atomicMax(&a.counters[kCntMaxWave], (unsigned long long)st_max);
+  }
 }
 
 // Apply staged block results after a wave (used when d exceeds the block
@@ -1309,7 +1339,7 @@ __global__ void fse_scatter_kernel(T* work, uint8_t* state, const FrameDesc* fra
                                    int gox, int goy) {
   const int item = blockIdx.x;
   const int fr = items[2 * item] & kItemFrameMask, bij = items[2 * item + 1];
-  const int bi = bij >> 16, bj = bij & 0xffff;
+  const int bi = (int)((unsigned)bij >> 16), bj = bij & 0xffff;
   const FrameDesc fd = frames[fr];
   const int nb = Bh * Bw;
   for (int s = threadIdx.x; s < nb; s += blockDim.x) {

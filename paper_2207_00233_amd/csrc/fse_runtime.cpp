@@ -593,6 +593,7 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
   a.zscale = (T)128.0;
   a.empty_fill = p.empty_fill;
   a.rerank_gap = p.rerank_gap > 0.0 ? p.rerank_gap : 1e-4;
+  a.counters = nullptr;
   const bool rerank = p.precision == FSE_FP32_RERANK;
   const bool mx = p.precision == FSE_FP32_F16X3;  // matrix-core transforms, 4 wavefronts
   // FP64 spectra: one slot per item of a step, per group (groups run at once)
@@ -606,6 +607,13 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
   if (rerank) {
     if ((rc = pl->spec64.reserve(std::max<int64_t>(1, spec_base[G]) * kSpecStride * sizeof(double))))
       return rc;
+  }
+  // re-scoring statistics of this call
+  if (rerank) {
+    if ((rc = pl->counters.reserve(kCntSlots * sizeof(unsigned long long))) ||
+        (rc = chk(hipMemsetAsync(pl->counters.ptr, 0, kCntSlots * sizeof(unsigned long long), s))))
+      return rc;
+    a.counters = (unsigned long long*)pl->counters.ptr;
   }
 
   // streams: group 0 on the plan's stream, the other groups on streams forked
@@ -725,6 +733,16 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
       }
     }
     if (hi > lo) busy += hi - lo;
+  }
+  pl->last.rescored = pl->last.rescore_candidates = pl->last.rescore_wide =
+      pl->last.rescore_max_wave = 0;
+  if (a.counters) {
+    unsigned long long cnt[kCntSlots];
+    if ((rc = chk(hipMemcpy(cnt, a.counters, sizeof(cnt), hipMemcpyDeviceToHost)))) return rc;
+    pl->last.rescored = (int64_t)cnt[kCntRescored];
+    pl->last.rescore_candidates = (int64_t)cnt[kCntCandidates];
+    pl->last.rescore_wide = (int64_t)cnt[kCntWide];
+    pl->last.rescore_max_wave = (int64_t)cnt[kCntMaxWave];
   }
   pl->last.kernel_ms = kms;
   pl->last.transform_ms = tms;
@@ -863,7 +881,7 @@ int32_t fse_plan_destroy(fse_plan_t pl) {
   for (hipEvent_t e : pl->gjoin) (void)hipEventDestroy(e);
   pl->gjoin.clear();
   DevBuf* bufs[] = {&pl->tbl_radial, &pl->tbl_twid, &pl->tbl_twid64, &pl->tbl_radial64,
-                    &pl->spec64, &pl->work, &pl->state,
+                    &pl->spec64, &pl->counters, &pl->work, &pl->state,
                     &pl->frames_dev, &pl->items_dev, &pl->u8_img, &pl->u8_lost, &pl->u8_out,
                     &pl->fout, &pl->staging, &pl->trace_u, &pl->trace_dc, &pl->flags_dev,
                     &pl->io_dev};

@@ -336,6 +336,7 @@ static void worker_loop(Serving* sv) {
   a.trace_dc = nullptr;
   a.spec64 = nullptr;
   a.rerank_gap = p.rerank_gap > 0.0 ? p.rerank_gap : 1e-4;
+  a.counters = nullptr;
   const bool rerank = p.precision == FSE_FP32_RERANK;
   const bool mx = p.precision == FSE_FP32_F16X3;  // matrix-core transforms, 4 wavefronts
 

@@ -3,12 +3,20 @@
 Tolerances (stated for this workload, on the 8-bit sample scale):
   * FSE_FP64: 1e-7 max-abs (teacher-forced and free-running); both sides
     compute the same sums in double, only the summation order differs.
-  * FSE_FP32: 0.5 max-abs per block when the block gets exactly the input
-    the oracle gets (teacher-forced), and 0.02 dB PSNR gap over the lost
-    samples of whole images run free.  Free-running max-abs is reported, not
-    bounded: the greedy selection is discontinuous at near-ties, so any
-    upstream difference (even one the oracle itself would make under a 1e-6
-    input change) can switch a later block to another, equally good model.
+  * FSE_FP32_RERANK (FP64 transforms, float iteration, exact re-scoring of
+    near ties): 0.5 max-abs for every block when the block gets exactly the
+    input the oracle gets (teacher-forced), and 0.02 dB PSNR gap over the
+    lost samples of whole images run free.  Free-running max-abs is
+    reported, not bounded: the greedy selection is discontinuous at
+    near-ties, so any upstream difference (even one the oracle itself would
+    make under a 1e-6 input change) can switch a later block to another,
+    equally good model.
+  * FSE_FP32 and FSE_FP32_F16X3 (float transforms) do NOT meet the 0.5
+    bar on every block: their spectra carry rounding of about 1e-7 of the
+    largest spectrum entry, which decides near ties differently from FP64 in
+    a few blocks in a hundred (measured worst 2.9 on the 8-bit scale).  Their
+    tests are characterizations, marked as such: the PSNR gap, the median
+    block error and the share of blocks within 0.5.
 Selected indices are compared modulo the mirror k -> -k, because a real
 residual gives exact ties |R[k]| = |R[-k]| whose choice does not change the
 real part of the model.
@@ -29,6 +37,15 @@ pytestmark = pytest.mark.gpu
 FP64_TOL = 1e-7
 FP32_TOL = 0.5
 PSNR_GAP = 0.02
+
+
+def below_bar_characterization(errs, label):
+    """FSE_FP32 / FSE_FP32_F16X3 (below the 0.5 bar, see the module
+    docstring): typical blocks agree, a few near ties go the other way."""
+    print(f"[below-bar] {label}: median {np.median(errs):.3e} max {errs.max():.3e}, "
+          f"{np.mean(errs <= FP32_TOL):.3f} within {FP32_TOL} over {len(errs)} blocks", flush=True)
+    assert np.median(errs) <= 0.05
+    assert np.mean(errs <= FP32_TOL) >= 0.9
 
 
 def oracle_params(p: fse.Params, nthreads=0) -> oracle.Params:
@@ -149,8 +166,8 @@ def test_fp64_trace_matches_oracle_trace():
 # float accumulation).  The bar: the first coefficient increment
 # gamma X[u] / W0 of every block within 1e-5 relative of the oracle's on the
 # same area (three split products lose ~2^-21 per term, float accumulation
-# ~1e-7 more), then the FP32 statistical bar per block (teacher-forced) and the
-# PSNR gap on whole images.
+# ~1e-7 more), and the PSNR gap on whole images; per block the mode is below
+# the 0.5 bar (characterized, see the module docstring).
 
 F16X3_DC_TOL = 1e-5
 
@@ -190,8 +207,7 @@ def test_f16x3_teacher_forced_blocks(seed):
         for b in seq])
     print(f"[parity] f16x3 teacher-forced median {np.median(errs):.3e} max {errs.max():.3e}, "
           f"{np.mean(errs <= FP32_TOL):.3f} within {FP32_TOL} over {len(seq)} blocks", flush=True)
-    assert np.median(errs) <= 0.05
-    assert np.mean(errs <= FP32_TOL) >= 0.9
+    below_bar_characterization(errs, "FSE_FP32_F16X3 teacher-forced")
 
 
 def test_f16x3_free_running_and_batch_identity():
@@ -225,8 +241,7 @@ def test_f16x3_reconstructed_samples_above_256():
         for b in seq])
     print(f"[parity] f16x3 bright texture: teacher-forced median {np.median(errs):.3e} "
           f"max {errs.max():.3e} over {len(seq)} blocks", flush=True)
-    assert np.median(errs) <= 0.05
-    assert np.mean(errs <= FP32_TOL) >= 0.9
+    below_bar_characterization(errs, "FSE_FP32_F16X3 bright texture")
 
 
 # ------------------------------------------------------------ edge cases
@@ -367,12 +382,11 @@ def test_maximum_area_f16x3_first_increment():
 # ------------------------------------------------------------ full size
 
 def test_config3_full_batch_sampled_blocks():
-    """The 64-frame mixed-resolution batch at K=200 in plain FP32, in one call
-    (the benchmark's launch configuration).  Properties at full size, and 24
-    seeded blocks against the oracle fed with the exact area each block saw:
-    plain FP32 decides rare near-ties (relative gap below its rounding drift)
-    differently from FP64, so the bar here is on the median and the share of
-    blocks within 0.5; the worst block is reported."""
+    """The 64-frame mixed-resolution batch at K=200 in plain FP32, in one call.
+    Properties at full size, and 24 seeded blocks against the oracle fed with
+    the exact area each block saw (FSE_FP32 is below the 0.5 bar: the share
+    within 0.5 and the median are characterized; the re-rank mode's test
+    below holds every block to 0.5)."""
     frames = synth.config3(seed=0)
     p = fse.Params(border_d=14, iterations=200, precision=fse.FSE_FP32)
     res = run_gpu(p, [f.image for f in frames], [f.lost for f in frames])
@@ -398,8 +412,7 @@ def test_config3_full_batch_sampled_blocks():
     errs = np.array(errs)
     print(f"[parity] FP32 full-size teacher-forced: median {np.median(errs):.3e} "
           f"max {errs.max():.3e} within 0.5: {np.mean(errs <= FP32_TOL):.3f}", flush=True)
-    assert np.median(errs) <= 0.05
-    assert np.mean(errs <= FP32_TOL) >= 0.9
+    below_bar_characterization(errs, "FSE_FP32 full-size batch")
 
 
 # ------------------------------------------------------------ FP32 + FP64 re-rank
@@ -541,9 +554,9 @@ SHAPES = {"4 wavefronts": "0,0", "8 wavefronts": "0,1000000", "16 wavefronts": "
 @pytest.mark.parametrize("precision", [fse.FSE_FP64, fse.FSE_FP32_RERANK, fse.FSE_FP32])
 def test_every_launch_shape_matches_oracle(monkeypatch, shape, precision):
     """Each workgroup shape (4, 8 or 16 wavefronts per block, forced for every
-    launch) against the oracle: FP64 free-running to 1e-7; the FP32 modes
-    teacher-forced per block (re-rank: every block within 0.5; plain FP32:
-    the statistical bar of its near-tie reading)."""
+    launch) against the oracle: FP64 free-running to 1e-7; FSE_FP32_RERANK
+    teacher-forced, every block within 0.5; FSE_FP32 characterized (below
+    the bar)."""
     monkeypatch.setenv("FSE_WAVE_THRESHOLDS", SHAPES[shape])
     if precision == fse.FSE_FP64:
         rng = np.random.default_rng(21)
@@ -564,10 +577,9 @@ def test_every_launch_shape_matches_oracle(monkeypatch, shape, precision):
     print(f"[parity] {shape} precision {precision}: teacher-forced median "
           f"{np.median(errs):.3e} max {errs.max():.3e} over {len(seq)} blocks", flush=True)
     if precision == fse.FSE_FP32_RERANK:
-        assert errs.max() <= FP32_TOL
+        assert errs.max() <= FP32_TOL, errs.max()
     else:
-        assert np.median(errs) <= 0.05
-        assert np.mean(errs <= FP32_TOL) >= 0.9
+        below_bar_characterization(errs, f"{shape} FSE_FP32")
 
 
 # ------------------------------------------------------------ host buffers

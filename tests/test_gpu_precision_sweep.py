@@ -6,9 +6,11 @@ every lost block teacher-forced (the oracle gets exactly the area the GPU
 block saw), and the PSNR gap of the free-running frames.  Bars, on the 8-bit
 sample scale:
   * FSE_FP64: max-abs <= 1e-7, index agreement 1.0 on every block;
-  * FSE_FP32_RERANK: max-abs <= 0.5 on every block, mean agreement >= 0.95;
-  * FSE_FP32, FSE_FP32_F16X3: median <= 0.05 and >= 90 % of blocks within
-    0.5 (a flipped near-tie selects another, equally good model);
+  * FSE_FP32_RERANK: max-abs <= 0.5 on every block, mean index agreement
+    >= 0.95;
+  * FSE_FP32, FSE_FP32_F16X3 (float transforms) are below that bar (their
+    transforms' rounding decides a few near ties differently); characterized:
+    median <= 0.05 and >= 90 % of blocks within 0.5;
   * every mode: PSNR gap <= 0.02 dB.
 """
 from concurrent.futures import ThreadPoolExecutor
@@ -95,5 +97,5 @@ def test_precision_sweep(oracle_runs, name, precision):
         assert errs.max() <= 1e-7 and agrees.min() == 1.0
     elif precision == fse.FSE_FP32_RERANK:
         assert errs.max() <= 0.5 and agrees.mean() >= 0.95
-    else:
+    else:  # below the bar: characterization only
         assert np.median(errs) <= 0.05 and np.mean(errs <= 0.5) >= 0.9
