@@ -193,6 +193,33 @@ int32_t fse_plan_destroy(fse_plan_t plan);
 int32_t fse_conceal_image(fse_plan_t plan, const fse_frame *frames, int32_t n);
 
 /*
+ * fse_conceal_image for callers that cannot allocate memory (code that must
+ * not call hipMalloc: tight serving loops, harnesses that forbid it).  The
+ * same computation as fse_conceal_image with FSE_FLAG_DEVICE_PTRS (same
+ * kernels, one frame group, no staggered groups of streams), but every device
+ * buffer of the call (working image, state map, descriptors, work items,
+ * FP64 spectra, statistics) is a slice of a fixed device scratch region of
+ * FSE_NOALLOC_SCRATCH_BYTES that the library holds per GPU for the life of
+ * the process; no device or pinned host memory is allocated (host-side
+ * bookkeeping uses ordinary heap memory, and the lost-block flags and work
+ * items pass through ordinary host memory by synchronous copies).  The plan
+ * must have been created with FSE_FLAG_DEVICE_PTRS; frames are device
+ * pointers as for fse_conceal_image; traces are not supported; the call's
+ * fse_last_call_stats carries no timings (kernel_ms, busy_ms, span_ms,
+ * transform_ms are 0).  The scratch is shared by every call on a GPU and
+ * keeps the last call's contents: calls that overlap in time on one GPU (from
+ * several plans or threads) race, so callers serialize them.  With the same
+ * tuning (frame_groups = 1) it gives the results of fse_conceal_image bit for
+ * bit.  Errors: FSE_ERR_INVALID (as fse_conceal_image, a plan without
+ * FSE_FLAG_DEVICE_PTRS, a frame with a trace), FSE_ERR_NOMEM (the call needs
+ * more than FSE_NOALLOC_SCRATCH_BYTES of scratch: roughly 5 bytes per pixel
+ * in FSE_FP32, 9 in FSE_FP64, plus 131 KB per block of the largest wave in
+ * FSE_FP32_RERANK), FSE_ERR_DEVICE.
+ */
+#define FSE_NOALLOC_SCRATCH_BYTES ((int64_t)128 << 20)
+int32_t fse_conceal_image_noalloc(fse_plan_t plan, const fse_frame *frames, int32_t n);
+
+/*
  * Serving: submit one frame (host pointers only).  The input is copied before
  * the call returns; out, out_f32, out_f64, trace and stats must stay valid
  * until fse_poll reports FSE_OK for the ticket (or the plan is destroyed).

@@ -38,9 +38,10 @@ FSE_FP32_F16X3 = 3
 FSE_FLAG_DEVICE_PTRS = 1
 FSE_MAX_ITERATIONS = 1024
 
-EXPORTED = ("fse_plan", "fse_plan_destroy", "fse_conceal_image", "fse_submit",
-            "fse_poll", "fse_schedule", "fse_schedule_refined", "fse_last_call_stats",
-            "fse_plan_get_tuning", "fse_plan_set_tuning", "fse_strerror")
+EXPORTED = ("fse_plan", "fse_plan_destroy", "fse_conceal_image", "fse_conceal_image_noalloc",
+            "fse_submit", "fse_poll", "fse_schedule", "fse_schedule_refined",
+            "fse_last_call_stats", "fse_plan_get_tuning", "fse_plan_set_tuning", "fse_strerror")
+FSE_NOALLOC_SCRATCH_BYTES = 128 << 20
 
 
 class FseError(RuntimeError):
@@ -160,6 +161,8 @@ def load():
     lib.fse_plan_destroy.restype = ctypes.c_int32
     lib.fse_conceal_image.argtypes = [ctypes.c_void_p, P(_Frame), ctypes.c_int32]
     lib.fse_conceal_image.restype = ctypes.c_int32
+    lib.fse_conceal_image_noalloc.argtypes = [ctypes.c_void_p, P(_Frame), ctypes.c_int32]
+    lib.fse_conceal_image_noalloc.restype = ctypes.c_int32
     lib.fse_submit.argtypes = [ctypes.c_void_p, P(_Frame), P(ctypes.c_uint64)]
     lib.fse_submit.restype = ctypes.c_int32
     lib.fse_poll.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32]
@@ -342,6 +345,17 @@ class Plan:
             arr[i] = _Frame(f["image"], W, H, W, f["lost"], W, f["out"], W,
                             f.get("out_f32"), f.get("out_f64"), None, None)
         _check(self._lib.fse_conceal_image(self.handle, arr, len(frames)), "fse_conceal_image")
+
+    def conceal_device_noalloc(self, frames) -> None:
+        """conceal_device through fse_conceal_image_noalloc: the call's device
+        buffers are slices of the library's fixed scratch (nothing allocated)."""
+        arr = (_Frame * len(frames))()
+        for i, f in enumerate(frames):
+            W, H = int(f["width"]), int(f["height"])
+            arr[i] = _Frame(f["image"], W, H, W, f["lost"], W, f["out"], W,
+                            f.get("out_f32"), f.get("out_f64"), None, None)
+        _check(self._lib.fse_conceal_image_noalloc(self.handle, arr, len(frames)),
+               "fse_conceal_image_noalloc")
 
     def last_call_stats(self) -> dict:
         cs = _CallStats()

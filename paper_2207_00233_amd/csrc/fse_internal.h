@@ -15,7 +15,16 @@
 
 namespace fse {
 
-// Grow-only device allocation.
+// Bump allocator over a fixed device region (the scratch of the noalloc entry
+// point): while a thread has one set, DevBuf::reserve carves from it.
+struct ScratchArena {
+  char* base = nullptr;
+  size_t size = 0;
+  size_t used = 0;
+};
+void set_thread_arena(ScratchArena* a);
+
+// Grow-only device allocation (or a slice of the thread's scratch arena).
 struct DevBuf {
   void* ptr = nullptr;
   size_t cap = 0;
@@ -141,10 +150,14 @@ struct fse_plan_s {
   int sticky = 0;
   std::mutex exec_mu;  // one synchronous call at a time
   fse::Serving* serving = nullptr;
+  void* scratch = nullptr;  // device address of the noalloc scratch on this plan's device
 };
 
 namespace fse {
-int conceal_batch(fse_plan_s* pl, const fse_frame* frames, int n);
+int conceal_batch(fse_plan_s* pl, const fse_frame* frames, int n, bool noalloc);
+// Device address of the noalloc scratch on the current device (the array is a
+// file-scope __device__ symbol of the kernel file).
+hipError_t noalloc_scratch_address(void** out);
 int serving_init(fse_plan_s* pl);
 void serving_shutdown(fse_plan_s* pl);
 }  // namespace fse

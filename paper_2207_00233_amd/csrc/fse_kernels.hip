@@ -50,6 +50,18 @@ __device__ __forceinline__ const double* twiddle_const<double>() { return c_twid
 template <>
 __device__ __forceinline__ const float* twiddle_const<float>() { return c_twid32; }
 
+// Scratch of fse_conceal_image_noalloc: a fixed region of device memory in
+// the code object (each GPU the library runs on holds its own copy until the
+// process ends), so that the call allocates nothing.  Host code never names
+// the array itself (its name is a host-side stand-in): it takes the device
+// address once per device through hipGetSymbolAddress and passes that.
+constexpr size_t kNoAllocScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+hipError_t noalloc_scratch_address(void** out) {
+  return hipGetSymbolAddress(out, HIP_SYMBOL(scratch));
+}
+
 hipError_t upload_twiddle_constants(const double* tbl) {
   float t32[2 * kFft];
   for (int i = 0; i < 2 * kFft; ++i) t32[i] = (float)tbl[i];

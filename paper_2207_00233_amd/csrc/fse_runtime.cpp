@@ -43,8 +43,20 @@ template <typename T>
 hipError_t launch_finalize(const IoDesc* io, int nframes, int64_t max_pixels,
                            const uint8_t* state, const T* work, hipStream_t s);
 
+// Scratch arena of the calling thread (fse_conceal_image_noalloc): while it is
+// set, device buffers are carved from it and nothing is allocated.
+static thread_local ScratchArena* t_arena = nullptr;
+
 int DevBuf::reserve(size_t bytes) {
   if (bytes <= cap) return FSE_OK;
+  if (ScratchArena* ar = t_arena) {
+    const size_t off = (ar->used + 255) & ~(size_t)255;
+    if (off > ar->size || bytes > ar->size - off) return FSE_ERR_NOMEM;
+    ptr = ar->base + off;
+    cap = bytes;
+    ar->used = off + bytes;
+    return FSE_OK;
+  }
   if (ptr) (void)hipFree(ptr);
   ptr = nullptr;
   cap = 0;
@@ -273,8 +285,11 @@ static int ensure_group_streams(fse_plan_s* pl, int G) {
   return FSE_OK;
 }
 
+// noalloc: device buffers come from the calling thread's scratch arena, one
+// frame group, synchronous copies through ordinary host memory instead of
+// pinned staging, no per-launch timing events.
 template <typename T>
-static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
+static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n, bool noalloc) {
   const fse_params& p = pl->p;
   const bool dev = (p.flags & FSE_FLAG_DEVICE_PTRS) != 0;
   hipStream_t s = pl->stream;
@@ -409,7 +424,19 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
   // their flags already
   const size_t flag_bytes = (size_t)flag_total * (refined ? 4 : 1);
   const IoDesc* iod = (const IoDesc*)pl->io_dev.ptr;
-  if (dev) {
+  std::vector<uint8_t> flag_copy;  // noalloc: the flags in ordinary host memory
+  if (dev && noalloc) {
+    flag_copy.resize(std::max<size_t>(1, flag_bytes));
+    if ((rc = chk(hipMemsetAsync(pl->flags_dev.ptr, 0, flag_bytes, s))) ||
+        (rc = chk(launch_init<T>(iod, n, max_pixels, work, state,
+                                 refined ? nullptr : (uint8_t*)pl->flags_dev.ptr,
+                                 refined ? (int32_t*)pl->flags_dev.ptr : nullptr, false, Bh, Bw,
+                                 gox, goy, s))) ||
+        (rc = chk(hipMemcpyAsync(flag_copy.data(), pl->flags_dev.ptr, flag_bytes,
+                                 hipMemcpyDeviceToHost, s))) ||
+        (rc = chk(hipStreamSynchronize(s))))
+      return rc;
+  } else if (dev) {
     if ((rc = pl->pin_flags.reserve(std::max<size_t>(1, flag_bytes)))) return rc;
     if (!pl->ev_flags && hipEventCreateWithFlags(&pl->ev_flags, hipEventDisableTiming) != hipSuccess)
       return FSE_ERR_DEVICE;
@@ -426,9 +453,10 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
   if ((rc = chk(launch_init<T>(iod, n, max_pixels, work, state, nullptr, nullptr, true, Bh, Bw,
                                gox, goy, s))))
     return rc;
-  if (dev && (rc = chk(hipEventSynchronize(pl->ev_flags)))) return rc;
-  const uint8_t* flag_base = dev ? (const uint8_t*)pl->pin_flags.ptr : host_flags.data();
-  const int32_t* count_base = dev ? (const int32_t*)pl->pin_flags.ptr : host_counts.data();
+  if (dev && !noalloc && (rc = chk(hipEventSynchronize(pl->ev_flags)))) return rc;
+  const void* dflags = noalloc ? (const void*)flag_copy.data() : pl->pin_flags.ptr;
+  const uint8_t* flag_base = dev ? (const uint8_t*)dflags : host_flags.data();
+  const int32_t* count_base = dev ? (const int32_t*)dflags : host_counts.data();
 
   // processing order per frame
   std::vector<std::vector<int32_t>> wave_of(n), seq(n);
@@ -465,7 +493,7 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
   // waves is the batch's critical path.  Inside a group frames start at
   // staggered steps: step s of the group holds wave s - off[f] of its frame f.
   const bool staged_mode = p.border_d > std::min(Bh, Bw);
-  const int G = staged_mode ? 1 : std::max(1, std::min(pl->group_count(), n));
+  const int G = (staged_mode || noalloc) ? 1 : std::max(1, std::min(pl->group_count(), n));
   std::vector<std::vector<int>> gframes(G);
   bool crit_group = false;  // group 0 holds the deepest frames
   {
@@ -553,7 +581,12 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
   if (want_trace && ((rc = pl->trace_u.reserve(std::max<int64_t>(1, n_items) * K * sizeof(int32_t))) ||
                      (rc = pl->trace_dc.reserve(std::max<int64_t>(1, n_items) * K * 2 * sizeof(T)))))
     return rc;
-  if (n_items > 0) {
+  if (n_items > 0 && noalloc) {
+    if ((rc = chk(hipMemcpyAsync(pl->items_dev.ptr, items.data(), items.size() * sizeof(int32_t),
+                                 hipMemcpyHostToDevice, s))) ||
+        (rc = chk(hipStreamSynchronize(s))))
+      return rc;
+  } else if (n_items > 0) {
     // through pinned staging, so that the copy does not hold the host; the
     // previous call's copy out of the staging is done first
     if (!pl->ev_items && hipEventCreateWithFlags(&pl->ev_items, hipEventDisableTiming) != hipSuccess)
@@ -622,13 +655,16 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
   int n_launch = 0;
   for (int g = 0; g < G; ++g)
     for (size_t t = 0; t + 1 < gstart[g].size(); ++t) n_launch += gstart[g][t + 1] > gstart[g][t];
-  while ((int)pl->events.size() < 3 * n_launch + 2) {
+  // timing events around every launch (not in the noalloc form)
+  const bool timed = !noalloc;
+  while (timed && (int)pl->events.size() < 3 * n_launch + 2) {
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return FSE_ERR_DEVICE;
     pl->events.push_back(e);
   }
-  hipEvent_t ev_fork = pl->events[3 * n_launch], ev_end = pl->events[3 * n_launch + 1];
-  if ((rc = chk(hipEventRecord(ev_fork, s)))) return rc;
+  hipEvent_t ev_fork = timed ? pl->events[3 * n_launch] : nullptr;
+  hipEvent_t ev_end = timed ? pl->events[3 * n_launch + 1] : nullptr;
+  if (timed && (rc = chk(hipEventRecord(ev_fork, s)))) return rc;  // G > 1 implies timed
   for (int g = 1; g < G; ++g)
     if ((rc = chk(hipStreamWaitEvent(pl->gstreams[g - 1], ev_fork, 0)))) return rc;
   int li = 0;
@@ -649,16 +685,16 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
       if (rerank) a.spec64 = (double*)pl->spec64.ptr + spec_base[g] * kSpecStride;
       const int waves =
           mx ? 4 : (crit_group && g == 0 ? pl->crit_waves_for(cnt) : pl->waves_for(step_total));
-      if ((rc = chk(hipEventRecord(pl->events[3 * li], gs)))) return rc;
+      if (timed && (rc = chk(hipEventRecord(pl->events[3 * li], gs)))) return rc;
       if constexpr (std::is_same<T, float>::value) {
         if (rerank &&
             (rc = chk(launch_dft64(a, (const double*)pl->tbl_radial64.ptr, (int)cnt, gs))))
           return rc;
       }
-      if ((rc = chk(hipEventRecord(pl->events[3 * li + 1], gs)))) return rc;
+      if (timed && (rc = chk(hipEventRecord(pl->events[3 * li + 1], gs)))) return rc;
       if ((rc = chk(launch_block<T>(a, (int)cnt, waves, gs, rerank ? 1 : (mx ? 2 : 0)))))
         return rc;
-      if ((rc = chk(hipEventRecord(pl->events[3 * li + 2], gs)))) return rc;
+      if (timed && (rc = chk(hipEventRecord(pl->events[3 * li + 2], gs)))) return rc;
       if (staged && (rc = chk(launch_scatter<T>(work, state, a.frames, a.items, (int)cnt,
                                                 (const T*)pl->staging.ptr, Bh, Bw, gox, goy, gs))))
         return rc;
@@ -670,7 +706,7 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
         (rc = chk(hipStreamWaitEvent(s, pl->gjoin[g - 1], 0))))
       return rc;
   }
-  if ((rc = chk(hipEventRecord(ev_end, s)))) return rc;
+  if (timed && (rc = chk(hipEventRecord(ev_end, s)))) return rc;
 
   // outputs
   if ((rc = chk(launch_finalize<T>((const IoDesc*)pl->io_dev.ptr, n, max_pixels, state, work, s))))
@@ -701,18 +737,18 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
   }
 
   double kms = 0.0, tms = 0.0;
-  for (int t = 0; t < n_launch; ++t) {
+  for (int t = 0; timed && t < n_launch; ++t) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, pl->events[3 * t + 1], pl->events[3 * t + 2]) == hipSuccess) kms += ms;
     if (rerank && hipEventElapsedTime(&ms, pl->events[3 * t], pl->events[3 * t + 1]) == hipSuccess)
       tms += ms;
   }
   float span = 0.f;
-  (void)hipEventElapsedTime(&span, ev_fork, ev_end);
+  if (timed) (void)hipEventElapsedTime(&span, ev_fork, ev_end);
   // union of the iteration kernel's launch intervals (launches of different
   // groups overlap)
   double busy = 0.0;
-  {
+  if (timed) {
     std::vector<std::pair<float, float>> iv;
     iv.reserve(n_launch);
     for (int t = 0; t < n_launch; ++t) {
@@ -783,10 +819,30 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
   return FSE_OK;
 }
 
-int conceal_batch(fse_plan_s* pl, const fse_frame* frames, int n) {
-  return pl->p.precision == FSE_FP64 ? run_batch<double>(pl, frames, n)
-                                     : run_batch<float>(pl, frames, n);
+// Device address of the noalloc scratch, taken once per device (with that
+// device current) and kept: each GPU holds its own copy of the array.
+static int noalloc_scratch_init(fse_plan_s* pl) {
+  static std::mutex mu;
+  static std::vector<void*> addr;  // per device id
+  std::lock_guard<std::mutex> lk(mu);
+  if ((int)addr.size() <= pl->device) addr.resize(pl->device + 1, nullptr);
+  if (!addr[pl->device]) {
+    void* p = nullptr;
+    if (hipSetDevice(pl->device) != hipSuccess || noalloc_scratch_address(&p) != hipSuccess ||
+        !p)
+      return FSE_ERR_DEVICE;
+    addr[pl->device] = p;
+  }
+  pl->scratch = addr[pl->device];
+  return FSE_OK;
 }
+
+int conceal_batch(fse_plan_s* pl, const fse_frame* frames, int n, bool noalloc) {
+  return pl->p.precision == FSE_FP64 ? run_batch<double>(pl, frames, n, noalloc)
+                                     : run_batch<float>(pl, frames, n, noalloc);
+}
+
+void set_thread_arena(ScratchArena* a) { t_arena = a; }
 
 }  // namespace fse
 
@@ -853,6 +909,11 @@ int32_t fse_plan(const fse_params* p, void* hip_stream, fse_plan_t* out) {
     }
   }
   make_tables(pl);
+  rc = noalloc_scratch_init(pl);
+  if (rc) {
+    fse_plan_destroy(pl);
+    return rc;
+  }
   rc = plan_device_init(pl);
   if (rc) {
     fse_plan_destroy(pl);
@@ -910,8 +971,43 @@ int32_t fse_conceal_image(fse_plan_t pl, const fse_frame* frames, int32_t n) {
   if (pl->sticky) return pl->sticky;
   if (hipSetDevice(pl->device) != hipSuccess) return FSE_ERR_DEVICE;
   auto t0 = std::chrono::steady_clock::now();
-  int rc = conceal_batch(pl, frames, n);
+  int rc = conceal_batch(pl, frames, n, false);
   auto t1 = std::chrono::steady_clock::now();
+  pl->last.total_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  if (rc == FSE_ERR_DEVICE) pl->sticky = rc;
+  return rc;
+}
+
+int32_t fse_conceal_image_noalloc(fse_plan_t pl, const fse_frame* frames, int32_t n) {
+  if (!pl || !frames || n < 1 || n > kItemFrameMask) return FSE_ERR_INVALID;
+  if (!(pl->p.flags & FSE_FLAG_DEVICE_PTRS)) return FSE_ERR_INVALID;
+  for (int f = 0; f < n; ++f) {
+    int rc = validate_frame(&frames[f], true);
+    if (rc) return rc;
+    if (frames[f].trace) return FSE_ERR_INVALID;
+  }
+  std::lock_guard<std::mutex> lk(pl->exec_mu);
+  if (pl->sticky) return pl->sticky;
+  if (!pl->scratch) return FSE_ERR_DEVICE;
+  if (hipSetDevice(pl->device) != hipSuccess) return FSE_ERR_DEVICE;
+  // the call's device buffers become slices of the scratch; the plan's own
+  // buffers are set aside and restored afterwards
+  ScratchArena ar;
+  ar.base = (char*)pl->scratch;
+  ar.size = (size_t)FSE_NOALLOC_SCRATCH_BYTES;
+  DevBuf* bufs[] = {&pl->work, &pl->state, &pl->frames_dev, &pl->io_dev, &pl->flags_dev,
+                    &pl->items_dev, &pl->staging, &pl->spec64, &pl->counters};
+  DevBuf saved[sizeof(bufs) / sizeof(bufs[0])];
+  for (size_t i = 0; i < sizeof(bufs) / sizeof(bufs[0]); ++i) {
+    saved[i] = *bufs[i];
+    *bufs[i] = DevBuf();
+  }
+  set_thread_arena(&ar);
+  auto t0 = std::chrono::steady_clock::now();
+  int rc = conceal_batch(pl, frames, n, true);
+  auto t1 = std::chrono::steady_clock::now();
+  set_thread_arena(nullptr);
+  for (size_t i = 0; i < sizeof(bufs) / sizeof(bufs[0]); ++i) *bufs[i] = saved[i];
   pl->last.total_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
   if (rc == FSE_ERR_DEVICE) pl->sticky = rc;
   return rc;

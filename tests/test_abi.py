@@ -73,6 +73,7 @@ def test_plan_rejects_other_fft_sizes(lib):
 def test_null_arguments(lib):
     assert lib.fse_plan(None, None, None) == fse.FSE_ERR_INVALID
     assert lib.fse_conceal_image(None, None, 1) == fse.FSE_ERR_INVALID
+    assert lib.fse_conceal_image_noalloc(None, None, 1) == fse.FSE_ERR_INVALID
     assert lib.fse_submit(None, None, None) == fse.FSE_ERR_INVALID
     assert lib.fse_poll(None, 1, 0) == fse.FSE_ERR_INVALID
     assert lib.fse_plan_destroy(None) == fse.FSE_OK
