@@ -12,6 +12,8 @@ Functions (see ``fse_oracle.c`` for the readings of the paper they take):
   * :func:`schedule_refined` -- the sample-count criterion Section 3 suggests
   * :func:`conceal`   -- a whole image, wave by wave, snapshot semantics
   * :func:`extract_area` -- the area and class map one block sees
+  * :func:`block3`, :func:`schedule3`, :func:`conceal3`, :func:`extract_area3`
+    -- the three-dimensional form for video volumes (``fse_oracle3d.c``)
 """
 from __future__ import annotations
 
@@ -25,6 +27,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "fse_oracle.c")
+_SRC3 = os.path.join(_HERE, "fse_oracle3d.c")  # the three-dimensional form
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 CLS_A, CLS_R, CLS_BI, CLS_BO, CLS_OUT = 0, 1, 2, 3, 4
@@ -34,10 +37,10 @@ ORDER_OPTIMIZED, ORDER_LINESCAN, ORDER_REFINED = 0, 1, 2
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (plain C, OpenMP over the blocks of a wave)."""
     if force or not os.path.exists(_LIB_PATH) or (
-            os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC)):
+            os.path.getmtime(_LIB_PATH) < max(os.path.getmtime(_SRC), os.path.getmtime(_SRC3))):
         tmp = _LIB_PATH + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared",
-                               "-Wall", "-o", tmp, _SRC, "-lm"])
+                               "-Wall", "-o", tmp, _SRC, _SRC3, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -92,6 +95,47 @@ class Params:
         return self.block_w + 2 * self.border_d
 
 
+class _Params3(ctypes.Structure):
+    _fields_ = [
+        ("block_t", ctypes.c_int32), ("block_h", ctypes.c_int32), ("block_w", ctypes.c_int32),
+        ("border_t", ctypes.c_int32), ("border_d", ctypes.c_int32),
+        ("fft_t", ctypes.c_int32), ("fft_h", ctypes.c_int32), ("fft_w", ctypes.c_int32),
+        ("rho", ctypes.c_double), ("delta", ctypes.c_double), ("gamma", ctypes.c_double),
+        ("iterations", ctypes.c_int32), ("order", ctypes.c_int32),
+        ("empty_fill", ctypes.c_double), ("nthreads", ctypes.c_int32),
+    ]
+
+
+@dataclasses.dataclass
+class Params3:
+    """Three-dimensional FSE of a video volume (frames x rows x columns):
+    blocks of block_t x block_h x block_w samples, areas extended by border_t
+    frames and border_d samples, basis grid fft_t x fft_h x fft_w."""
+    block_t: int = 1
+    block_h: int = 16
+    block_w: int = 16
+    border_t: int = 2
+    border_d: int = 8
+    fft_t: int = 8
+    fft_h: int = 32
+    fft_w: int = 32
+    rho: float = 0.8
+    delta: float = 0.2
+    gamma: float = 0.5
+    iterations: int = 100
+    order: int = ORDER_OPTIMIZED
+    empty_fill: float = 128.0
+    nthreads: int = 0
+
+    def c(self) -> _Params3:
+        return _Params3(**dataclasses.asdict(self))
+
+    @property
+    def shape(self):
+        return (self.block_t + 2 * self.border_t, self.block_h + 2 * self.border_d,
+                self.block_w + 2 * self.border_d)
+
+
 _lib = None
 
 
@@ -124,6 +168,25 @@ def _load():
             P(_Params), ctypes.c_int, ctypes.c_int, P(ctypes.c_double),
             P(ctypes.c_uint8), ctypes.c_int, ctypes.c_int, P(ctypes.c_double),
             P(ctypes.c_uint8)]
+        lib.oracle3_block.restype = ctypes.c_int
+        lib.oracle3_block.argtypes = [
+            P(_Params3), ctypes.c_int, ctypes.c_int, ctypes.c_int, P(ctypes.c_double),
+            P(ctypes.c_double), P(ctypes.c_uint8), P(ctypes.c_double),
+            P(ctypes.c_int32), P(ctypes.c_double), P(ctypes.c_double),
+            P(ctypes.c_double), P(ctypes.c_double), ctypes.c_int]
+        lib.oracle3_schedule.restype = ctypes.c_int
+        lib.oracle3_schedule.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                         P(ctypes.c_uint8), ctypes.c_int,
+                                         P(ctypes.c_int32), P(ctypes.c_int32)]
+        lib.oracle3_conceal.restype = ctypes.c_int
+        lib.oracle3_conceal.argtypes = [
+            P(_Params3), ctypes.c_int, ctypes.c_int, ctypes.c_int, P(ctypes.c_double),
+            P(ctypes.c_uint8), P(ctypes.c_double), P(ctypes.c_int32)]
+        lib.oracle3_extract_area.restype = None
+        lib.oracle3_extract_area.argtypes = [
+            P(_Params3), ctypes.c_int, ctypes.c_int, ctypes.c_int, P(ctypes.c_double),
+            P(ctypes.c_uint8), ctypes.c_int, ctypes.c_int, ctypes.c_int,
+            P(ctypes.c_double), P(ctypes.c_uint8)]
         _lib = lib
     return _lib
 
@@ -260,4 +323,94 @@ def extract_area(params: Params, image: np.ndarray, state: np.ndarray,
     lib.oracle_extract_area(ctypes.byref(pc), H, W, _ptr(img, ctypes.c_double),
                             _ptr(st, ctypes.c_uint8), int(bi), int(bj),
                             _ptr(f, ctypes.c_double), _ptr(cls, ctypes.c_uint8))
+    return f, cls
+
+
+# ------------------------------------------------------------------ 3-D form
+
+def block3(params: Params3, f: np.ndarray, cls: np.ndarray,
+           spec_iter: Optional[int] = None) -> BlockResult:
+    """Three-dimensional FSE over one area (values ``f`` and classes ``cls``,
+    both Mt x M x N); a complex ``f`` is accepted as a test signal."""
+    lib = _load()
+    f_im = None
+    if np.iscomplexobj(f):
+        f_im = np.ascontiguousarray(f.imag, dtype=np.float64)
+        f = f.real
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    cls = np.ascontiguousarray(cls, dtype=np.uint8)
+    Mt, M, N = f.shape
+    assert cls.shape == f.shape
+    K = params.iterations
+    F = params.fft_t * params.fft_h * params.fft_w
+    g = np.zeros(f.shape, np.float64)
+    u = np.zeros(K, np.int32)
+    dc = np.zeros(2 * K, np.float64)
+    e = np.zeros(K + 1, np.float64)
+    w0 = np.zeros(1, np.float64)
+    spec = np.zeros(2 * F, np.float64) if spec_iter is not None else None
+    pc = params.c()
+    rc = lib.oracle3_block(ctypes.byref(pc), Mt, M, N, _ptr(f, ctypes.c_double),
+                           _ptr(f_im, ctypes.c_double), _ptr(cls, ctypes.c_uint8),
+                           _ptr(g, ctypes.c_double), _ptr(u, ctypes.c_int32),
+                           _ptr(dc, ctypes.c_double), _ptr(e, ctypes.c_double),
+                           _ptr(w0, ctypes.c_double), _ptr(spec, ctypes.c_double),
+                           -1 if spec_iter is None else int(spec_iter))
+    sp = None
+    if spec is not None:
+        sp = (spec[0::2] + 1j * spec[1::2]).reshape(params.fft_t, params.fft_h, params.fft_w)
+    return BlockResult(g, u, dc[0::2] + 1j * dc[1::2], e, float(w0[0]), rc == 1, sp)
+
+
+def schedule3(lost_blocks: np.ndarray, order: int = ORDER_OPTIMIZED):
+    """Processing order of a (frames, rows, columns) block grid over the
+    26-neighbourhood: (waves, wave index per block, sequence)."""
+    lib = _load()
+    lb = np.ascontiguousarray(lost_blocks, dtype=np.uint8)
+    tb, hb, wb = lb.shape
+    wave = np.zeros(lb.size, np.int32)
+    seq = np.zeros(max(1, lb.size), np.int32)
+    nw = lib.oracle3_schedule(tb, hb, wb, _ptr(lb, ctypes.c_uint8), int(order),
+                              _ptr(wave, ctypes.c_int32), _ptr(seq, ctypes.c_int32))
+    return nw, wave.reshape(tb, hb, wb), seq[:int((lb != 0).sum())]
+
+
+@dataclasses.dataclass
+class Conceal3Result:
+    volume: np.ndarray     # float64 [T, H, W]
+    waves: int
+    wave_of: np.ndarray    # int32 [tb, hb, wb]
+
+
+def conceal3(params: Params3, volume: np.ndarray, lost: np.ndarray) -> Conceal3Result:
+    """Conceal the lost samples of a volume (values of lost samples ignored)."""
+    lib = _load()
+    vol = np.ascontiguousarray(volume, dtype=np.float64)
+    ls = np.ascontiguousarray(lost, dtype=np.uint8)
+    T, H, W = vol.shape
+    tb, hb, wb = -(-T // params.block_t), -(-H // params.block_h), -(-W // params.block_w)
+    out = np.zeros(vol.shape, np.float64)
+    wave = np.zeros(tb * hb * wb, np.int32)
+    pc = params.c()
+    nw = lib.oracle3_conceal(ctypes.byref(pc), T, H, W, _ptr(vol, ctypes.c_double),
+                             _ptr(ls, ctypes.c_uint8), _ptr(out, ctypes.c_double),
+                             _ptr(wave, ctypes.c_int32))
+    if nw < 0:
+        raise ValueError("invalid oracle parameters")
+    return Conceal3Result(out, nw, wave.reshape(tb, hb, wb))
+
+
+def extract_area3(params: Params3, volume: np.ndarray, state: np.ndarray,
+                  bt: int, bi: int, bj: int):
+    """Values and classes of the 3-D area of block (bt, bi, bj)."""
+    lib = _load()
+    vol = np.ascontiguousarray(volume, dtype=np.float64)
+    st = np.ascontiguousarray(state, dtype=np.uint8)
+    T, H, W = vol.shape
+    f = np.zeros(params.shape, np.float64)
+    cls = np.zeros(params.shape, np.uint8)
+    pc = params.c()
+    lib.oracle3_extract_area(ctypes.byref(pc), T, H, W, _ptr(vol, ctypes.c_double),
+                             _ptr(st, ctypes.c_uint8), int(bt), int(bi), int(bj),
+                             _ptr(f, ctypes.c_double), _ptr(cls, ctypes.c_uint8))
     return f, cls
