@@ -239,6 +239,39 @@ int32_t fse_submit(fse_plan_t plan, const fse_frame *frame, uint64_t *ticket);
 int32_t fse_poll(fse_plan_t plan, uint64_t ticket, int32_t timeout_us);
 
 /*
+ * Device memory of serving.  device_mem_budget bounds every device buffer the
+ * serving worker holds: the per-pixel arenas (working image, state map, 8-bit
+ * input, mask, output) and the per-step buffers (FP64 spectra in
+ * FSE_FP32_RERANK, staged results when d exceeds the block size, work items),
+ * which take a fixed share of it (a quarter with spectra or staging, else
+ * 1/64).  A frame is admitted while its pixels fit the arenas and its largest
+ * wave fits the per-step share beside the largest waves of the frames already
+ * admitted; fse_submit returns FSE_ERR_NOMEM for a frame that never fits.
+ *   budget          device_mem_budget in effect (bytes);
+ *   device_bytes    device memory the serving worker holds (0 before the
+ *                   first fse_submit), at most `budget`;
+ *   peak_committed  most bytes ever committed to admitted frames at once
+ *                   (their pixels in the arenas plus their largest waves in
+ *                   the per-step buffers), at most device_bytes;
+ *   admitted_frames frames admitted so far;  peak_frames: most at once;
+ *   step_blocks_cap blocks of a step the per-step share holds;
+ *   peak_step_blocks most blocks ever reserved at once for the largest waves
+ *                   of the admitted frames (at most step_blocks_cap).
+ * Errors: FSE_ERR_INVALID (null pointer).
+ */
+typedef struct {
+  int64_t budget;
+  int64_t device_bytes;
+  int64_t peak_committed;
+  int64_t admitted_frames;
+  int32_t peak_frames;
+  int32_t reserved;
+  int64_t step_blocks_cap;
+  int64_t peak_step_blocks;
+} fse_serving_stats;
+int32_t fse_plan_serving_stats(fse_plan_t plan, fse_serving_stats *out);
+
+/*
  * Processing order only (paper Algorithm 1 / line scan) for a block grid of
  * hb x wb blocks; lost[hb*wb] nonzero marks blocks with samples to
  * extrapolate (FSE_ORDER_REFINED needs sample counts: fse_schedule_refined).  wave_of[hb*wb] receives the wave index (-1 for the other
@@ -333,6 +366,74 @@ typedef struct {
 } fse_tuning;
 int32_t fse_plan_get_tuning(fse_plan_t plan, fse_tuning *out);
 int32_t fse_plan_set_tuning(fse_plan_t plan, const fse_tuning *t);
+
+/*
+ * Three-dimensional FSE of a video volume.  The paper develops the processing
+ * order for two-dimensional signals and names its extension to
+ * higher-dimensional signals through three-dimensional FSE (conclusion); this
+ * interface carries every 2-D definition over one more dimension:
+ *   - the volume (frames x rows x columns) is divided into blocks of
+ *     block_t x block_h x block_w samples; a block holding lost samples is
+ *     extrapolated from its area, the block plus border_t frames before and
+ *     after and border_d samples around it in each frame (nominal geometry at
+ *     the volume's faces, samples outside weigh 0);
+ *   - weighting function of Eq. (2) with the 3-D distance from the area's
+ *     centre; basis phi_k[t,m,n] = exp(+j 2 pi (k1 t / fft_t + k2 m / fft_h
+ *     + k3 n / fft_w)) with the area at the grid's first corner; selection,
+ *     increment, tie rule and iteration count as in two dimensions (ties to
+ *     the smallest (k1 fft_h + k2) fft_w + k3); output = real part, rounded
+ *     half to even and clamped;
+ *   - processing order: Algorithm 1 over the 26-neighbourhood of the block
+ *     grid (a missing neighbour at a face counts as not extrapolated, the
+ *     wave filled in raster order frame, row, column), or line scan; every
+ *     block of a wave reads the volume as it was at the start of the wave.
+ * This build supports the basis grid fft_t x fft_h x fft_w = 8 x 32 x 32 and
+ * FSE_FP64 (FSE_ERR_UNSUPPORTED otherwise): one workgroup per block holds the
+ * whole 3-D spectrum in LDS.
+ */
+typedef struct fse_plan3_s *fse_plan3_t; /* opaque, owned by the library */
+
+typedef struct {
+  int32_t block_t, block_h, block_w; /* >= 1; block + 2 border <= fft per dimension */
+  int32_t border_t;                  /* frames before and after the block, >= 0 */
+  int32_t border_d;                  /* samples around the block in each frame, >= 0 */
+  int32_t fft_t, fft_h, fft_w;       /* basis grid; this build: 8 x 32 x 32 */
+  double rho;                        /* weighting decay, (0, 1] */
+  double delta;                      /* reconstructed-area weight, [0, 1] */
+  double gamma;                      /* orthogonality deficiency compensation, (0, 1] */
+  int32_t iterations;                /* K, 1..FSE_MAX_ITERATIONS */
+  int32_t order;                     /* FSE_ORDER_OPTIMIZED or FSE_ORDER_LINESCAN */
+  int32_t precision;                 /* FSE_FP64 */
+  double empty_fill;                 /* value written when an area has no support */
+} fse_params3;
+
+typedef struct {
+  const uint8_t *volume; /* frames * height * width samples, frame-major, contiguous */
+  const uint8_t *lost;   /* same layout, nonzero = lost (values there are ignored) */
+  int32_t frames, height, width;
+  uint8_t *out;          /* same layout; may alias volume; known samples copied */
+  double *out_f64;       /* nullable: unquantized result, same layout */
+  fse_stats *stats;      /* nullable: waves, lost blocks, largest wave */
+} fse_volume;
+
+/* Create / destroy a 3-D plan (host buffers; work on the given HIP stream,
+ * nullable = the library's own).  Errors: FSE_ERR_INVALID (null pointer,
+ * parameter out of range, block + 2 border above the grid),
+ * FSE_ERR_UNSUPPORTED (another grid or precision), FSE_ERR_DEVICE. */
+int32_t fse_plan3(const fse_params3 *p, void *hip_stream, fse_plan3_t *out);
+int32_t fse_plan3_destroy(fse_plan3_t plan);
+
+/* Conceal one volume synchronously (host pointers; the call returns with the
+ * result in `out`).  Errors: FSE_ERR_INVALID (null pointers, sizes <= 0 or
+ * above 65535 per dimension), FSE_ERR_DEVICE. */
+int32_t fse_conceal_volume(fse_plan3_t plan, const fse_volume *v);
+
+/* Processing order only, for a tb x hb x wb block grid (frame-major);
+ * lost[b] nonzero marks blocks with samples to extrapolate; wave_of[b]
+ * receives the wave (-1 for the others), seq (nullable) the lost blocks in
+ * processing order.  Returns the number of waves or FSE_ERR_INVALID. */
+int32_t fse_schedule3(int32_t tb, int32_t hb, int32_t wb, const uint8_t *lost, int32_t order,
+                      int32_t *wave_of, int32_t *seq);
 
 /* Static description of an error code. */
 const char *fse_strerror(int32_t code);

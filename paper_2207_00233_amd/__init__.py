@@ -40,7 +40,9 @@ FSE_MAX_ITERATIONS = 1024
 
 EXPORTED = ("fse_plan", "fse_plan_destroy", "fse_conceal_image", "fse_conceal_image_noalloc",
             "fse_submit", "fse_poll", "fse_schedule", "fse_schedule_refined",
-            "fse_last_call_stats", "fse_plan_get_tuning", "fse_plan_set_tuning", "fse_strerror")
+            "fse_last_call_stats", "fse_plan_get_tuning", "fse_plan_set_tuning",
+            "fse_plan_serving_stats", "fse_plan3", "fse_plan3_destroy", "fse_conceal_volume",
+            "fse_schedule3", "fse_strerror")
 FSE_NOALLOC_SCRATCH_BYTES = 128 << 20
 
 
@@ -94,6 +96,30 @@ class _Frame(ctypes.Structure):
                 ("out", ctypes.c_void_p), ("out_stride", ctypes.c_int32),
                 ("out_f32", ctypes.c_void_p), ("out_f64", ctypes.c_void_p),
                 ("trace", ctypes.POINTER(_Trace)), ("stats", ctypes.POINTER(_Stats))]
+
+
+class _ServingStats(ctypes.Structure):
+    _fields_ = [("budget", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("peak_committed", ctypes.c_int64), ("admitted_frames", ctypes.c_int64),
+                ("peak_frames", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("step_blocks_cap", ctypes.c_int64), ("peak_step_blocks", ctypes.c_int64)]
+
+
+class _Params3(ctypes.Structure):
+    _fields_ = [("block_t", ctypes.c_int32), ("block_h", ctypes.c_int32),
+                ("block_w", ctypes.c_int32), ("border_t", ctypes.c_int32),
+                ("border_d", ctypes.c_int32), ("fft_t", ctypes.c_int32),
+                ("fft_h", ctypes.c_int32), ("fft_w", ctypes.c_int32),
+                ("rho", ctypes.c_double), ("delta", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("iterations", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("empty_fill", ctypes.c_double)]
+
+
+class _Volume(ctypes.Structure):
+    _fields_ = [("volume", ctypes.c_void_p), ("lost", ctypes.c_void_p),
+                ("frames", ctypes.c_int32), ("height", ctypes.c_int32), ("width", ctypes.c_int32),
+                ("out", ctypes.c_void_p), ("out_f64", ctypes.c_void_p),
+                ("stats", ctypes.POINTER(_Stats))]
 
 
 class _CallStats(ctypes.Structure):
@@ -179,6 +205,17 @@ def load():
     lib.fse_plan_get_tuning.restype = ctypes.c_int32
     lib.fse_plan_set_tuning.argtypes = [ctypes.c_void_p, P(_Tuning)]
     lib.fse_plan_set_tuning.restype = ctypes.c_int32
+    lib.fse_plan_serving_stats.argtypes = [ctypes.c_void_p, P(_ServingStats)]
+    lib.fse_plan_serving_stats.restype = ctypes.c_int32
+    lib.fse_plan3.argtypes = [P(_Params3), ctypes.c_void_p, P(ctypes.c_void_p)]
+    lib.fse_plan3.restype = ctypes.c_int32
+    lib.fse_plan3_destroy.argtypes = [ctypes.c_void_p]
+    lib.fse_plan3_destroy.restype = ctypes.c_int32
+    lib.fse_conceal_volume.argtypes = [ctypes.c_void_p, P(_Volume)]
+    lib.fse_conceal_volume.restype = ctypes.c_int32
+    lib.fse_schedule3.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                  ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+    lib.fse_schedule3.restype = ctypes.c_int32
     lib.fse_strerror.argtypes = [ctypes.c_int32]
     lib.fse_strerror.restype = ctypes.c_char_p
     _lib = lib
@@ -357,6 +394,13 @@ class Plan:
         _check(self._lib.fse_conceal_image_noalloc(self.handle, arr, len(frames)),
                "fse_conceal_image_noalloc")
 
+    def serving_stats(self) -> dict:
+        """Device memory of serving (fse_plan_serving_stats)."""
+        st = _ServingStats()
+        _check(self._lib.fse_plan_serving_stats(self.handle, ctypes.byref(st)),
+               "fse_plan_serving_stats")
+        return {k: getattr(st, k) for k, _ in _ServingStats._fields_ if k != "reserved"}
+
     def last_call_stats(self) -> dict:
         cs = _CallStats()
         _check(self._lib.fse_last_call_stats(self.handle, ctypes.byref(cs)), "fse_last_call_stats")
@@ -416,3 +460,82 @@ def fse_submit(plan: Plan, image, lost, **kw) -> int:
 
 def fse_poll(plan: Plan, ticket: int, timeout_us: int = 0):
     return plan.fse_poll(ticket, timeout_us)
+
+
+# ------------------------------------------------------------ 3-D (video volumes)
+
+@dataclasses.dataclass
+class Params3:
+    """fse_params3: three-dimensional FSE of a volume (frames x rows x
+    columns) on the 8 x 32 x 32 basis grid of this build, FP64."""
+    block_t: int = 1
+    block_h: int = 16
+    block_w: int = 16
+    border_t: int = 2
+    border_d: int = 8
+    fft_t: int = 8
+    fft_h: int = 32
+    fft_w: int = 32
+    rho: float = 0.8
+    delta: float = 0.2
+    gamma: float = 0.5
+    iterations: int = 100
+    order: int = FSE_ORDER_OPTIMIZED
+    precision: int = FSE_FP64
+    empty_fill: float = 128.0
+
+    def c(self) -> _Params3:
+        return _Params3(**dataclasses.asdict(self))
+
+
+class Plan3:
+    """fse_plan3 / fse_plan3_destroy / fse_conceal_volume (host arrays)."""
+
+    def __init__(self, params: Params3, hip_stream: Optional[int] = None):
+        self._lib = load()
+        self.params = params
+        self._pc = params.c()
+        h = ctypes.c_void_p()
+        _check(self._lib.fse_plan3(ctypes.byref(self._pc), hip_stream, ctypes.byref(h)),
+               "fse_plan3")
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            self._lib.fse_plan3_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def conceal_volume(self, volume: np.ndarray, lost: np.ndarray,
+                       want_float: bool = False) -> Result:
+        vol = np.ascontiguousarray(volume, dtype=np.uint8)
+        ls = np.ascontiguousarray(lost, dtype=np.uint8)
+        if vol.ndim != 3 or ls.shape != vol.shape:
+            raise ValueError("volume and lost must be frames x height x width")
+        out = np.empty_like(vol)
+        of = np.empty(vol.shape, np.float64) if want_float else None
+        st = _Stats()
+        T, H, W = vol.shape
+        v = _Volume(vol.ctypes.data, ls.ctypes.data, T, H, W, out.ctypes.data,
+                    of.ctypes.data if of is not None else None, ctypes.pointer(st))
+        _check(self._lib.fse_conceal_volume(self.handle, ctypes.byref(v)), "fse_conceal_volume")
+        return Result(out, of, st.waves, st.lost_blocks, st.max_wave_blocks)
+
+
+def schedule3(lost_blocks: np.ndarray, order: int = FSE_ORDER_OPTIMIZED):
+    """fse_schedule3: (waves, wave index per block, sequence) of a
+    (frames, rows, columns) block grid."""
+    lib = load()
+    lb = np.ascontiguousarray(lost_blocks, dtype=np.uint8)
+    tb, hb, wb = lb.shape
+    wave = np.zeros(max(1, lb.size), np.int32)
+    seq = np.zeros(max(1, lb.size), np.int32)
+    nw = lib.fse_schedule3(tb, hb, wb, lb.ctypes.data, order, wave.ctypes.data, seq.ctypes.data)
+    if nw < 0:
+        raise FseError(nw, "fse_schedule3")
+    return nw, wave[:lb.size].reshape(lb.shape), seq[:int((lb != 0).sum())]

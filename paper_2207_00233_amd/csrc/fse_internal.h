@@ -28,7 +28,8 @@ void set_thread_arena(ScratchArena* a);
 struct DevBuf {
   void* ptr = nullptr;
   size_t cap = 0;
-  int reserve(size_t bytes);
+  int reserve(size_t bytes);        // grows with 25 % slack
+  int reserve_exact(size_t bytes);  // grows to exactly `bytes` (for memory budgets)
   void release();
 };
 

@@ -69,6 +69,20 @@ int DevBuf::reserve(size_t bytes) {
   return FSE_OK;
 }
 
+int DevBuf::reserve_exact(size_t bytes) {
+  if (bytes <= cap) return FSE_OK;
+  if (t_arena) return reserve(bytes);
+  if (ptr) (void)hipFree(ptr);
+  ptr = nullptr;
+  cap = 0;
+  if (hipMalloc(&ptr, bytes) != hipSuccess) {
+    ptr = nullptr;
+    return FSE_ERR_DEVICE;
+  }
+  cap = bytes;
+  return FSE_OK;
+}
+
 void DevBuf::release() {
   if (ptr) (void)hipFree(ptr);
   ptr = nullptr;

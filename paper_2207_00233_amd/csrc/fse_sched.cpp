@@ -215,4 +215,81 @@ std::vector<int> stagger_frames(const std::vector<std::vector<int>>& sizes, doub
   return off;
 }
 
+// Three-dimensional order: the grid padded by one layer of outside cells on
+// every face, so the 26 neighbours of a cell are at fixed offsets; N per
+// pending cell = its not-extrapolated neighbours (outside or lost and not yet
+// done); each wave takes the cells with the smallest N in raster order
+// (frame, row, column) unless a 26-neighbour is already in the wave; after
+// the wave every pending neighbour of a taken cell loses one.
+int schedule_blocks3(int tb, int hb, int wb, const uint8_t* lost, int order, int32_t* wave_of,
+                     std::vector<int32_t>* seq) {
+  const int nb = tb * hb * wb;
+  for (int b = 0; b < nb; ++b) wave_of[b] = -1;
+  if (seq) seq->clear();
+  if (nb <= 0) return 0;
+  if (order == 1) {
+    int w = 0;
+    for (int b = 0; b < nb; ++b)
+      if (lost[b]) {
+        wave_of[b] = w++;
+        if (seq) seq->push_back(b);
+      }
+    return w;
+  }
+  const int W2 = wb + 2, H2 = hb + 2, T2 = tb + 2, plane = W2 * H2, n2 = plane * T2;
+  std::vector<int> nbr;
+  for (int a = -1; a <= 1; ++a)
+    for (int di = -1; di <= 1; ++di)
+      for (int dj = -1; dj <= 1; ++dj)
+        if (a || di || dj) nbr.push_back(a * plane + di * W2 + dj);
+  auto pad = [&](int t, int i, int j) { return ((t + 1) * H2 + i + 1) * W2 + j + 1; };
+  std::vector<uint8_t> open(n2, 1);  // 1: not extrapolated (outside, or lost and pending)
+  std::vector<int32_t> cell_of(n2, -1);
+  for (int t = 0; t < tb; ++t)
+    for (int i = 0; i < hb; ++i)
+      for (int j = 0; j < wb; ++j) {
+        const int b = (t * hb + i) * wb + j, c = pad(t, i, j);
+        open[c] = lost[b] ? 1 : 0;
+        cell_of[c] = b;
+      }
+  std::vector<int> cnt(n2, -1);
+  int npending = 0;
+  for (int c = 0; c < n2; ++c) {
+    if (cell_of[c] < 0 || !lost[cell_of[c]]) continue;
+    int k = 0;
+    for (int o : nbr) k += open[c + o];
+    cnt[c] = k;
+    ++npending;
+  }
+  std::vector<uint8_t> taken(n2, 0);
+  std::vector<int> wave;
+  int waves = 0;
+  while (npending > 0) {
+    int nmin = 1 << 30;
+    for (int c = 0; c < n2; ++c)
+      if (cnt[c] >= 0 && cnt[c] < nmin) nmin = cnt[c];
+    wave.clear();
+    for (int c = 0; c < n2; ++c) {  // padded raster order = (frame, row, column)
+      if (cnt[c] != nmin) continue;
+      bool clash = false;
+      for (int o : nbr) clash |= taken[c + o] != 0;
+      if (clash) continue;
+      taken[c] = 1;
+      wave.push_back(c);
+    }
+    for (int c : wave) {
+      taken[c] = 0;
+      cnt[c] = -1;
+      open[c] = 0;
+      wave_of[cell_of[c]] = waves;
+      if (seq) seq->push_back(cell_of[c]);
+      --npending;
+      for (int o : nbr)
+        if (cnt[c + o] >= 0) --cnt[c + o];
+    }
+    ++waves;
+  }
+  return waves;
+}
+
 }  // namespace fse

@@ -19,6 +19,13 @@ int schedule_blocks(int hb, int wb, const uint8_t* lost, int order, int32_t* wav
 int schedule_blocks_refined(int hb, int wb, const int32_t* unknown, int32_t outside,
                             int32_t* wave_of, std::vector<int32_t>* seq);
 
+// Processing order of a tb x hb x wb block grid of a video volume (frames,
+// rows, columns) for three-dimensional FSE: Algorithm 1 over the
+// 26-neighbourhood (a missing neighbour at the volume's faces counts as not
+// extrapolated), or line scan (order 1).  Same outputs as schedule_blocks.
+int schedule_blocks3(int tb, int hb, int wb, const uint8_t* lost, int order, int32_t* wave_of,
+                     std::vector<int32_t>* seq);
+
 // Start offsets (in launch steps) for the frames of a batch; sizes[f][t] is the
 // number of blocks of wave t of frame f.  See fse_sched.cpp.
 std::vector<int> stagger_frames(const std::vector<std::vector<int>>& sizes, double latency_us,

@@ -5,9 +5,15 @@
 // block flags (lost-sample counts) and the processing order on the caller's
 // thread, and queues it.
 // One worker thread per plan:
-//   - admits queued frames while the device arena (device_mem_budget) and the
-//     slot count (max_inflight_frames) allow, uploads them and builds their
-//     working image and state map;
+//   - admits queued frames while the device memory budget (device_mem_budget)
+//     and the slot count (max_inflight_frames) allow, uploads them and builds
+//     their working image and state map.  The budget covers every device
+//     buffer the worker holds: the per-pixel arenas (working image, state map,
+//     8-bit input, mask and output) and the per-step buffers (FP64 spectra in
+//     re-rank mode, staging when d exceeds the block, work items), which get
+//     a fixed share of it; a frame is admitted only while its pixels fit the
+//     arenas and its largest wave fits, beside the largest waves of the frames
+//     already admitted, the per-step share;
 //   - launches one step at a time: a step holds the next wave of every
 //     admitted frame, so frames that arrive while others run join the very
 //     next steps and their work overlaps on the device;
@@ -155,6 +161,7 @@ struct Req {
   std::vector<int32_t> seq;        // lost blocks in processing order
   std::vector<int32_t> wave_start; // start of every wave in seq, plus the end
   int nwaves = 0, next_wave = 0;
+  int max_wave = 0;  // blocks of the largest wave (per-step buffer share)
   int64_t off = -1;  // element offset in the arenas
   int slot = -1;     // index in the device frame tables
   hipEvent_t done_ev = nullptr;
@@ -194,6 +201,17 @@ struct Serving {
   HostBuf host_desc;  // per-slot staging of FrameDesc + IoDesc updates
   int max_slots = 64;
   int64_t budget = 0;
+  // per-step buffers: bytes per block of a step, their share of the budget in
+  // blocks, and the blocks reserved for the largest waves of admitted frames
+  int64_t per_block_step = 0;
+  int64_t step_blocks_cap = 0;
+  int64_t step_blocks = 0;
+  // accounting reported by fse_serving_stats
+  int64_t device_bytes = 0;   // device memory the worker holds
+  int64_t peak_admitted = 0;  // most bytes ever committed to admitted frames
+  int peak_frames = 0;        // most frames admitted at once
+  int64_t peak_step_blocks = 0;  // most per-step blocks committed at once
+  int64_t admitted_total = 0;
 };
 
 static int tsize(const fse_plan_s* pl) { return pl->p.precision == FSE_FP64 ? 8 : 4; }
@@ -202,25 +220,61 @@ static int tsize(const fse_plan_s* pl) { return pl->p.precision == FSE_FP64 ? 8 
 int serving_init(fse_plan_s* pl) {
   Serving* sv = new Serving();
   sv->pl = pl;
-  sv->max_slots = pl->p.max_inflight_frames > 0 ? pl->p.max_inflight_frames : 64;
-  sv->budget = pl->p.device_mem_budget > 0 ? pl->p.device_mem_budget : (int64_t)4 << 30;
+  const fse_params& p = pl->p;
+  sv->max_slots = p.max_inflight_frames > 0 ? p.max_inflight_frames : 64;
+  sv->budget = p.device_mem_budget > 0 ? p.device_mem_budget : (int64_t)4 << 30;
   sv->elem_bytes = tsize(pl) + 4;  // work, state, image, lost, out
+  // per step and block: FP64 spectra (re-rank), staged results (d > block),
+  // and the work item in each of the kAhead + 1 step slots
+  const bool rerank = p.precision == FSE_FP32_RERANK;
+  const bool staged = p.border_d > std::min(p.block_h, p.block_w);
+  sv->per_block_step = (rerank ? kSpecStride * (int64_t)sizeof(double) : 0) +
+                       (staged ? (int64_t)p.block_h * p.block_w * tsize(pl) : 0) +
+                       (kAhead + 1) * 2 * (int64_t)sizeof(int32_t);
+  // their share: a quarter of the budget when they hold spectra or staged
+  // results, else 1/64 (work items only)
+  const int64_t share = (rerank || staged) ? sv->budget / 4 : sv->budget / 64;
+  sv->step_blocks_cap = share / sv->per_block_step;
   pl->serving = sv;
   return FSE_OK;
+}
+
+// Bytes committed to the admitted frames (caller holds mu).
+static int64_t committed_bytes(const Serving* sv) {
+  return sv->arena.used_elems() * sv->elem_bytes + sv->step_blocks * sv->per_block_step;
 }
 
 // Device resources are created on first use so plans used only for
 // synchronous calls do not hold the serving arena.
 static int serving_start(Serving* sv) {
   fse_plan_s* pl = sv->pl;
-  const int64_t elems = sv->budget / sv->elem_bytes;
+  const fse_params& p = pl->p;
+  const bool rerank = p.precision == FSE_FP32_RERANK;
+  const bool staged = p.border_d > std::min(p.block_h, p.block_w);
+  const int64_t nb = std::max<int64_t>(1, sv->step_blocks_cap);
+  // descriptors and the per-step buffers first, the pixel arenas get the rest
+  const int64_t fixed = (int64_t)sv->max_slots * (sizeof(FrameDesc) + sizeof(IoDesc)) +
+                        sv->step_blocks_cap * sv->per_block_step;
+  const int64_t elems = std::max<int64_t>(0, sv->budget - fixed) / sv->elem_bytes;
   sv->arena.reset(elems);
-  if (sv->d_work.reserve(elems * tsize(pl)) || sv->d_state.reserve(elems) ||
-      sv->d_img.reserve(elems) || sv->d_lost.reserve(elems) || sv->d_out.reserve(elems) ||
-      sv->d_frames.reserve(sv->max_slots * sizeof(FrameDesc)) ||
-      sv->d_io.reserve(sv->max_slots * sizeof(IoDesc)) ||
+  if (sv->d_work.reserve_exact(elems * tsize(pl)) || sv->d_state.reserve_exact(elems) ||
+      sv->d_img.reserve_exact(elems) || sv->d_lost.reserve_exact(elems) ||
+      sv->d_out.reserve_exact(elems) ||
+      sv->d_frames.reserve_exact(sv->max_slots * sizeof(FrameDesc)) ||
+      sv->d_io.reserve_exact(sv->max_slots * sizeof(IoDesc)) ||
+      (rerank && sv->d_spec64.reserve_exact(nb * kSpecStride * sizeof(double))) ||
+      (staged && sv->d_staging.reserve_exact(nb * p.block_h * p.block_w * tsize(pl))) ||
       sv->host_desc.reserve((size_t)sv->max_slots * (sizeof(FrameDesc) + sizeof(IoDesc))))
     return FSE_ERR_DEVICE;
+  for (auto& st : sv->ring)
+    if (st.items.reserve_exact(nb * 2 * sizeof(int32_t)) ||
+        st.host.reserve(nb * 2 * sizeof(int32_t)))
+      return FSE_ERR_DEVICE;
+  sv->device_bytes = 0;
+  for (const DevBuf* b : {&sv->d_work, &sv->d_state, &sv->d_img, &sv->d_lost, &sv->d_out,
+                          &sv->d_frames, &sv->d_io, &sv->d_spec64, &sv->d_staging})
+    sv->device_bytes += (int64_t)b->cap;
+  for (auto& st : sv->ring) sv->device_bytes += (int64_t)st.items.cap;
   for (auto& st : sv->ring)
     if (hipEventCreateWithFlags(&st.ev, hipEventDisableTiming) != hipSuccess) return FSE_ERR_DEVICE;
   for (int s = sv->max_slots - 1; s >= 0; --s) sv->free_slots.push_back(s);
@@ -374,8 +428,12 @@ static void worker_loop(Serving* sv) {
       }
       while (!sv->stop && !sv->queue.empty() && !sv->free_slots.empty()) {
         auto& r = sv->queue.front();
+        // the frame's largest wave must fit the per-step share beside the
+        // largest waves of the frames already admitted
+        if (sv->step_blocks + r->max_wave > sv->step_blocks_cap) break;
         const int64_t off = sv->arena.alloc((int64_t)r->H * r->W);
         if (off < 0) break;  // wait until running frames free the arena
+        sv->step_blocks += r->max_wave;
         r->off = off;
         r->slot = sv->free_slots.back();
         sv->free_slots.pop_back();
@@ -383,6 +441,10 @@ static void worker_loop(Serving* sv) {
         admitted.push_back(r);
         sv->active.push_back(r);
         sv->queue.pop_front();
+        sv->admitted_total += 1;
+        sv->peak_admitted = std::max(sv->peak_admitted, committed_bytes(sv));
+        sv->peak_frames = std::max(sv->peak_frames, (int)sv->active.size());
+        sv->peak_step_blocks = std::max(sv->peak_step_blocks, sv->step_blocks);
       }
     }
     for (auto& r : admitted)
@@ -449,6 +511,7 @@ static void worker_loop(Serving* sv) {
         worker_complete<T>(sv, r);
         std::lock_guard<std::mutex> lk(sv->mu);
         sv->arena.release(r->off);
+        sv->step_blocks -= r->max_wave;
         sv->free_slots.push_back(r->slot);
         r->st = St::kDone;
         sv->active.erase(sv->active.begin() + i);
@@ -525,6 +588,8 @@ int32_t fse_submit(fse_plan_t pl, const fse_frame* f, uint64_t* ticket) {
   Serving* sv = pl->serving;
   const fse_params& p = pl->p;
   const int64_t px = (int64_t)f->height * f->width;
+  // can never fit: more pixels than the arenas hold (checked against the
+  // budget here, against the arenas once the worker has started)
   if (((px + 255) & ~255LL) > sv->budget / sv->elem_bytes) return FSE_ERR_NOMEM;
   {
     std::lock_guard<std::mutex> lk(sv->mu);
@@ -603,13 +668,25 @@ int32_t fse_submit(fse_plan_t pl, const fse_frame* f, uint64_t* ticket) {
     while (q < r->seq.size() && wave_of[r->seq[q]] < (int)t) ++q;
     r->wave_start[t] = (int32_t)q;
   }
+  for (int t = 0; t < r->nwaves; ++t)
+    r->max_wave = std::max(r->max_wave, r->wave_start[t + 1] - r->wave_start[t]);
   if (f->stats) {
     f->stats->waves = r->nwaves;
     f->stats->lost_blocks = (int32_t)r->seq.size();
-    int best = 0;
-    for (int t = 0; t < r->nwaves; ++t) best = std::max(best, r->wave_start[t + 1] - r->wave_start[t]);
-    f->stats->max_wave_blocks = best;
+    f->stats->max_wave_blocks = r->max_wave;
     f->stats->latency_ms = 0.0;
+  }
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    // a frame whose pixels or largest wave exceed what the budget ever holds
+    const bool too_big = r->max_wave > sv->step_blocks_cap ||
+                         (sv->started && ((px + 255) & ~255LL) > sv->arena.capacity());
+    if (too_big) {
+      sv->pinned.put(r->pin_in);
+      sv->pinned.put(r->pin_out);
+      (void)hipEventDestroy(r->done_ev);
+      return FSE_ERR_NOMEM;
+    }
   }
   if (f->trace) f->trace->count = 0;  // traces are recorded by fse_conceal_image only
   {
@@ -620,6 +697,21 @@ int32_t fse_submit(fse_plan_t pl, const fse_frame* f, uint64_t* ticket) {
     *ticket = r->ticket;
   }
   sv->cv_work.notify_all();
+  return FSE_OK;
+}
+
+int32_t fse_plan_serving_stats(fse_plan_t pl, fse_serving_stats* out) {
+  if (!pl || !out) return FSE_ERR_INVALID;
+  Serving* sv = pl->serving;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  out->budget = sv->budget;
+  out->device_bytes = sv->started ? sv->device_bytes : 0;
+  out->peak_committed = sv->peak_admitted;
+  out->admitted_frames = sv->admitted_total;
+  out->peak_frames = sv->peak_frames;
+  out->reserved = 0;
+  out->step_blocks_cap = sv->step_blocks_cap;
+  out->peak_step_blocks = sv->peak_step_blocks;
   return FSE_OK;
 }
 

@@ -315,3 +315,23 @@ def serving_stream(seed: int = 0, n_frames: int = 240, rate_hz: float = 240.0,
         out.append(Arrival(t, Frame(img, lost)))
     return out
 
+
+
+@dataclasses.dataclass
+class Volume:
+    volume: np.ndarray  # uint8 [T, H, W] ground truth
+    lost: np.ndarray    # uint8 [T, H, W], 1 = lost
+
+
+def video_volume(seed: int = 0, frames: int = 6, height: int = 64, width: int = 80,
+                 block: int = 16, p: float = 0.2, fps: float = 30.0) -> Volume:
+    """``frames`` consecutive drifting-texture frames (one scene, sampled at
+    ``fps``); 16 x 16 blocks of every frame lost i.i.d. with probability p,
+    independently per frame, so lost blocks have known samples in the same
+    block position of neighbouring frames."""
+    rng = np.random.default_rng(seed)
+    scene_seed = int(rng.integers(0, 2**31 - 1))
+    vol = np.stack([drifting_frame(np.random.default_rng(scene_seed), height, width, z / fps, rng)
+                    for z in range(frames)])
+    lost = np.stack([bernoulli_block_loss(rng, height, width, block, p) for _ in range(frames)])
+    return Volume(vol, lost)

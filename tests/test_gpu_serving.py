@@ -51,6 +51,15 @@ def test_admission_under_a_small_budget():
     with fse.Plan(p) as plan:
         tickets = [plan.fse_submit(im, ls) for im, ls in frames]
         res = [plan.fse_poll(t, timeout_us=-1) for t in tickets]
+        st = plan.serving_stats()
+        print(f"[serve] small budget: {st}", flush=True)
+        # every device buffer of the worker lies within the budget, and the
+        # frames admitted at once never committed more than it
+        assert st["budget"] == p.device_mem_budget
+        assert 0 < st["device_bytes"] <= st["budget"]
+        assert 0 < st["peak_committed"] <= st["device_bytes"]
+        assert st["admitted_frames"] == len(frames)
+        assert 2 <= st["peak_frames"] <= 2
         # a frame larger than the whole budget can never be admitted
         big = np.zeros((256, 256), np.uint8)
         with pytest.raises(fse.FseError) as ei:
@@ -97,3 +106,32 @@ def test_destroy_with_frames_in_flight():
     for im, ls in frames:
         plan.fse_submit(im, ls)
     plan.close()   # waits for in-flight work, frees everything
+
+
+def test_rerank_spectra_count_against_the_budget():
+    """Re-rank mode's per-step FP64 spectra (131 KB per block of a step) take
+    their share of the budget: with a budget whose share holds 1.5 times the
+    largest wave of these frames, the admitted frames' largest waves never
+    exceed the share (so not all frames run at once, although their pixels
+    would fit several times over), and results equal the alone run."""
+    frames = _frames(3, [(64, 96)] * 5)
+    p0 = fse.Params(border_d=14, iterations=40, precision=fse.FSE_FP32_RERANK)
+    ref = _alone(p0, frames)
+    max_wave = max(a.max_wave_blocks for a in ref)
+    per_block = (4 * 64 * 64 + 32) * 8 + 3 * 8  # FP64 spectra + work items per step block
+    budget = int(4 * 1.5 * max_wave * per_block)  # a quarter of it is the per-step share
+    p = fse.Params(border_d=14, iterations=40, precision=fse.FSE_FP32_RERANK,
+                   device_mem_budget=budget, max_inflight_frames=16)
+    with fse.Plan(p) as plan:
+        tickets = [plan.fse_submit(im, ls, want_float=True) for im, ls in frames]
+        res = [plan.fse_poll(t, timeout_us=-1) for t in tickets]
+        st = plan.serving_stats()
+    print(f"[serve] re-rank budget {budget}: {st}", flush=True)
+    assert 0 < st["device_bytes"] <= budget and st["peak_committed"] <= st["device_bytes"]
+    # the share holds 1.5 largest waves: never two frames with the largest wave
+    # at once, and never all five frames although their pixels would fit
+    assert max_wave <= st["step_blocks_cap"] < 2 * max_wave
+    assert 0 < st["peak_step_blocks"] <= st["step_blocks_cap"]
+    assert st["peak_frames"] < len(frames)
+    for r, a in zip(res, ref):
+        np.testing.assert_array_equal(r.out_f, a.out_f)

@@ -154,6 +154,23 @@ def test_initial_spectrum_matches_numpy_fftn():
     np.testing.assert_allclose(res.spectrum, np.fft.fftn(x), rtol=1e-10, atol=1e-8)
 
 
+def test_known_frames_at_odd_offsets_only_tie_k1_and_k1_plus_4():
+    # Degenerate case of the 3-D method: known samples only at area frames
+    # t = 1 and t = 3 (one lost frame between two known ones, the others
+    # outside the volume).  On the 8-frame grid e^{-j 2 pi 4 t / 8} = -1 for
+    # odd t, so R[k1 + 4] = -R[k1]: every selection is an exact tie between
+    # two frequencies of opposite sign on the lost frame t = 2.
+    rng = np.random.default_rng(11)
+    f = rng.uniform(0.0, 255.0, (5, 32, 32))
+    cls = np.full((5, 32, 32), oracle.CLS_OUT, np.uint8)
+    cls[1] = cls[3] = oracle.CLS_A
+    cls[2] = oracle.CLS_BO
+    cls[2, 8:24, 8:24] = oracle.CLS_BI
+    p = oracle.Params3(iterations=1)
+    sp = oracle.block3(p, f, cls, spec_iter=0).spectrum
+    np.testing.assert_allclose(sp[4:], -sp[:4], rtol=0, atol=1e-9 * np.abs(sp).max())
+
+
 @pytest.mark.parametrize("it", [0, 3, 9])
 def test_parseval_3d(it):
     rng = np.random.default_rng(4)
