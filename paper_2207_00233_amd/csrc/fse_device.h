@@ -129,34 +129,10 @@ __host__ __device__ inline LdsLayout lds_layout(int M, int N, int K, int waves, 
   return L;
 }
 
-// LDS of the FP64 transform pass of the re-rank mode (4 wavefronts): the
-// staged x = f w and w (double, pitch N | 1), then over the same bytes the
-// real row DFTs of x and w (M x 33 complex double each), then the
-// column-DFT exchange (4 wavefronts x 8 rows x 64 columns complex double, one
-// half of the rows at a time) with the mirrored rows of the packed columns
-// 0 / 32 behind it; twiddles and slots after the region.
-constexpr int64_t kDftExchange = 4LL * 8 * kFft * 16;  // bytes
-constexpr int64_t kDftPacked = 2LL * kFft * 16;        // bytes
-__host__ __device__ inline LdsLayout dft_layout(int M, int N, int waves) {
-  LdsLayout L;
-  const int NP = N | 1;
-  L.cs = 0;  // unused
-  const int64_t stage = 2LL * M * NP * 8;
-  L.bx = 0;
-  L.bw = (int64_t)M * kHalf * 16;
-  const int64_t rows = 2 * L.bw;
-  int64_t region = stage > rows ? stage : rows;
-  if (region < kDftExchange + kDftPacked) region = kDftExchange + kDftPacked;
-  region = align16(region);
-  L.hist_dc = L.hist_u = region;  // unused
-  L.tw64 = region;
-  L.twt = L.tw64 + kFft * 2 * 8;
-  L.slots = align16(L.twt + kFft * 2 * 8);
-  L.cand = L.slots + 2LL * waves * 32;
-  L.misc = align16(L.cand);
-  L.total = L.misc + 32;
-  return L;
-}
+// LDS of the FP64 transform pass of the re-rank mode: the 64 x 64 complex
+// double grid with a pad entry after every 8 (row pitch 72), the 64
+// twiddles, 4 partial sums.
+constexpr int64_t kDftLdsBytes = 64LL * 72 * 16 + 64 * 16 + 32;
 
 template <typename T>
 inline int64_t lds_bytes(int M, int N, int K, int waves, bool stage_needed = true) {

@@ -758,168 +758,200 @@ __device__ __forceinline__ void load_twiddles(unsigned char* smem, const LdsLayo
 
 // FP64 transform pass of the re-rank mode: writes R0 = DFT(x), W = DFT(w)
 // and W0 of every work item in double to BlockArgs::spec64 (the iteration
-// kernel runs in float).  4 wavefronts.
-//  A: gather and weight the area: x = f w and w staged in double.
-//  B: real row DFTs of x and w (lane = row m, wavefront w takes the columns
-//     k2 = w + 4q <= 32), written over the dead staging.
-//  C: 64-point DFTs down 64 column sources at once, one per lane: lanes 0-31
-//     take x, lanes 32-63 take w; lane c >= 1 of a half takes column c, lane
-//     0 takes columns 0 and 32 packed as Y[m][0] + j Y[m][32] (both real for
-//     a real area).  The DFT is factorized 4 x 16 (wavefront w sums the rows
-//     m = w + 4 m1 for 16 outputs; the partial sums meet in LDS, one half of
-//     the outputs at a time, so the exchange needs 32 KB).  A column c >= 1
-//     gives X[k1][c] and, by conjugate symmetry, X[-k1][64 - c]; the packed
-//     column is unpacked with its mirrored rows.  No exchange buffer for the
-//     unpacking of a z = x + j s w transform: the outputs go to HBM, where
-//     the symmetry is applied on writing.  LDS ~49 KB at a 44 x 44 area
-//     (the staging, 31 KB, lies under the row DFTs), three workgroups per CU.
-__global__ __launch_bounds__(256, 3) void fse_dft64_kernel(BlockArgs<float> a,
+// kernel runs in float).  One workgroup of 4 wavefronts per item; x = f w and
+// then w go through the same steps, each on its own (a packed transform of
+// x + j s w would leak the rounding of one into the other: a black area
+// would not give X = 0 exactly):
+//  A: gather and weight the area (Eq. (2)) onto the 64 x 64 grid in LDS
+//     (zeros outside the area);
+//  B: the 2-D DFT as 64-point transforms along rows, then along columns,
+//     each factorized 8 x 8: an 8-point DFT over n1 of z[8 n1 + n2], the
+//     twiddle e^{-j 2 pi n2 k1 / 64}, an 8-point DFT over n2 (output
+//     k1 + 8 k2).  Every 8-point DFT runs in one thread's registers, in
+//     place: the position 8 a + b of a row holds after the pass the frequency
+//     a + 8 b.  A row of 64 positions is stored as 8 groups of 8 with one pad
+//     entry per group, so that the eight lanes of a group of lanes hit
+//     distinct banks in both access patterns;
+//  C: the spectrum out in coalesced rows of 1 KB.
+// LDS 74 KB: two workgroups per CU.
+namespace {
+
+constexpr int kDp = 72;  // row pitch of the FP64 transform grid (complex)
+
+__device__ __forceinline__ int dpos(int p) { return p + (p >> 3); }
+
+// v * e^{-j theta} with t = (cos theta, sin theta)
+__device__ __forceinline__ double2 dmul_conj(double2 v, double2 t) {
+  return make_double2(fma(v.x, t.x, v.y * t.y), fma(v.y, t.x, -v.x * t.y));
+}
+
+__device__ __forceinline__ double2 dadd(double2 a, double2 b) {
+  return make_double2(a.x + b.x, a.y + b.y);
+}
+__device__ __forceinline__ double2 dsub(double2 a, double2 b) {
+  return make_double2(a.x - b.x, a.y - b.y);
+}
+
+// out[k] = sum_n v[n] e^{-j 2 pi n k / 8}, in place: two 4-point DFTs of the
+// even and odd samples, joined with the factors e^{-j 2 pi k / 8}
+__device__ __forceinline__ void dft8(double2 (&v)[8]) {
+  constexpr double c = 0.70710678118654752440;  // 1 / sqrt(2)
+  double2 e[4], o[4];
+  {
+    const double2 t0 = dadd(v[0], v[4]), t1 = dsub(v[0], v[4]);
+    const double2 t2 = dadd(v[2], v[6]), t3 = dsub(v[2], v[6]);
+    e[0] = dadd(t0, t2);
+    e[2] = dsub(t0, t2);
+    e[1] = make_double2(t1.x + t3.y, t1.y - t3.x);  // t1 - j t3
+    e[3] = make_double2(t1.x - t3.y, t1.y + t3.x);  // t1 + j t3
+  }
+  {
+    const double2 t0 = dadd(v[1], v[5]), t1 = dsub(v[1], v[5]);
+    const double2 t2 = dadd(v[3], v[7]), t3 = dsub(v[3], v[7]);
+    o[0] = dadd(t0, t2);
+    o[2] = dsub(t0, t2);
+    o[1] = make_double2(t1.x + t3.y, t1.y - t3.x);
+    o[3] = make_double2(t1.x - t3.y, t1.y + t3.x);
+  }
+  // o[k] e^{-j 2 pi k / 8}: k = 1: c (1 - j), k = 2: -j, k = 3: -c (1 + j)
+  const double2 p1 = make_double2(c * (o[1].x + o[1].y), c * (o[1].y - o[1].x));
+  const double2 p2 = make_double2(o[2].y, -o[2].x);
+  const double2 p3 = make_double2(c * (o[3].y - o[3].x), -c * (o[3].x + o[3].y));
+  v[0] = dadd(e[0], o[0]);
+  v[4] = dsub(e[0], o[0]);
+  v[1] = dadd(e[1], p1);
+  v[5] = dsub(e[1], p1);
+  v[2] = dadd(e[2], p2);
+  v[6] = dsub(e[2], p2);
+  v[3] = dadd(e[3], p3);
+  v[7] = dsub(e[3], p3);
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(256, 2) void fse_dft64_kernel(BlockArgs<float> a,
                                                            const double* radial64) {
-  constexpr int WAVES = 4, ROWS = kFft / WAVES, QB = (kHalf + WAVES - 1) / WAVES;
+  constexpr int WAVES = 4;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  double2* Z = reinterpret_cast<double2*>(smem);          // 64 rows x kDp
+  double2* tw = Z + kFft * kDp;                            // 64 x (cos, sin)
+  double* red = reinterpret_cast<double*>(tw + kFft);      // 4 partial sums
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = uniform_int(tid >> 6);
-  const int M = a.M, N = a.N, NP = N | 1;
-  const LdsLayout L = dft_layout(M, N, WAVES);
+  const int M = a.M, N = a.N;
   const int item = blockIdx.x;
   const int fw = a.items[2 * item], bij = a.items[2 * item + 1];
   const int fr = fw & kItemFrameMask;
   if (fw >> kItemPrioShift) __builtin_amdgcn_s_setprio(2);
   const int bi = (int)((unsigned)bij >> 16), bj = bij & 0xffff;
   const FrameDesc fd = a.frames[fr];
-  const int by0 = bi * a.Bh - a.goy, bx0 = bj * a.Bw - a.gox;
-  const double W0 = gather_area<double, float, WAVES, false>(
-      smem, L, M, N, radial64, a.delta64, a.work + fd.off, a.state + fd.off, fd.H, fd.W,
-      by0 - a.d, bx0 - a.d, lane, wave);
+  const float* img = a.work + fd.off;
+  const uint8_t* st = a.state + fd.off;
+  const int oy = bi * a.Bh - a.goy - a.d, ox = bj * a.Bw - a.gox - a.d;
   double* out = a.spec64 + (int64_t)item * kSpecStride;
-  if (tid == 0) out[kSpecW0] = W0;
-  if (!(W0 > 0.0)) return;  // uniform
-  const double* xs = reinterpret_cast<const double*>(smem);  // staged x = f w, then w
-  const double* ws = xs + M * NP;
-  const double* twt = c_twid64;  // wave-uniform indices: scalar loads
-  double* bx = reinterpret_cast<double*>(smem + L.bx);
-  double* bw = reinterpret_cast<double*>(smem + L.bw);
-  double* zx = reinterpret_cast<double*>(smem);                 // C exchange
-  double* pk = reinterpret_cast<double*>(smem + kDftExchange);  // packed columns
 
-  // ---- B: real row DFTs ----
-  {
-    double axr[QB], axi[QB], awr[QB], awi[QB];
-#pragma unroll
-    for (int q = 0; q < QB; ++q) axr[q] = axi[q] = awr[q] = awi[q] = 0.0;
-    if (lane < M) {
-      for (int n = 0; n < N; ++n) {
-        const double xv = xs[lane * NP + n], wv = ws[lane * NP + n];
-#pragma unroll
-        for (int q = 0; q < QB; ++q) {
-          const int t = ((wave + WAVES * q) * n) & (kFft - 1);
-          const double cc = twt[2 * t], ss = twt[2 * t + 1];
-          axr[q] = fma(xv, cc, axr[q]);
-          axi[q] = fma(-xv, ss, axi[q]);
-          awr[q] = fma(wv, cc, awr[q]);
-          awi[q] = fma(-wv, ss, awi[q]);
-        }
+  if (tid < kFft) tw[tid] = make_double2(a.twid64[2 * tid], a.twid64[2 * tid + 1]);
+  const int n = lane, x = ox + n;
+  const bool xin = n < N && x >= 0 && x < fd.W;
+  const int pp = dpos(lane);
+  const int k2 = lane, c2 = dpos(8 * (k2 & 7) + (k2 >> 3));
+  double W0 = 0.0;
+  for (int pass = 0; pass < 2; ++pass) {  // 0: x = f w, 1: w
+    // ---- A: gather and weight; every grid position is written ----
+    double wsum = 0.0;
+    for (int m = wave; m < kFft; m += WAVES) {
+      const int y = oy + m;
+      double wv = 0.0, f = 0.0;
+      if (m < M && xin && y >= 0 && y < fd.H) {
+        const int64_t p = (int64_t)y * fd.W + x;
+        const uint8_t s = st[p];
+        const double fac = s == kKnown ? 1.0 : (s == kRecon ? a.delta64 : 0.0);
+        wv = radial64[m * N + n] * fac;
+        f = (double)img[p];
       }
+      wsum += wv;
+      Z[m * kDp + dpos(n)] = make_double2(pass ? wv : f * wv, 0.0);
     }
-    __syncthreads();  // the staging is dead
-    if (lane < M) {
+    if (pass == 0) {
+      wsum = wave_sum(wsum);
+      if (lane == 0) red[wave] = wsum;
+    }
+    __syncthreads();
+    if (pass == 0) {
 #pragma unroll
-      for (int q = 0; q < QB; ++q) {
-        const int k2 = wave + WAVES * q;
-        if (k2 < kHalf) {
-          bx[(lane * kHalf + k2) * 2] = axr[q];
-          bx[(lane * kHalf + k2) * 2 + 1] = axi[q];
-          bw[(lane * kHalf + k2) * 2] = awr[q];
-          bw[(lane * kHalf + k2) * 2 + 1] = awi[q];
-        }
+      for (int q = 0; q < WAVES; ++q) W0 += red[q];
+      if (tid == 0) out[kSpecW0] = W0;
+      if (!(W0 > 0.0)) return;  // uniform
+    }
+
+    // ---- B: rows (only the M rows of the area are non-zero) ----
+    // task (m, n2): 8-point DFT over n1 of z[m][8 n1 + n2], then the twiddle
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int t = tid + 256 * q, m = t >> 3, n2 = t & 7;
+      if (m < M) {
+        double2* r = Z + m * kDp + n2;
+        double2 v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = r[9 * i];
+        dft8(v);
+#pragma unroll
+        for (int kk = 1; kk < 8; ++kk) v[kk] = dmul_conj(v[kk], tw[n2 * kk]);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) r[9 * i] = v[i];
       }
     }
     __syncthreads();
-  }
-
-  // ---- C: column DFTs, lane = column source ----
-  const int part = lane >> 5, c = lane & 31;
-  const double* src = part ? bw : bx;
-  const int i_re = c == 0 ? 0 : 2 * c;               // Y[m][c].re, or Y[m][0].re
-  const int i_im = c == 0 ? 2 * (kFft / 2) : 2 * c + 1;  // Y[m][c].im, or Y[m][32].re
-  double pr[ROWS], pi[ROWS];  // partial 16-point DFTs of the rows m = wave + 4 m1
+    // task (m, k1): 8-point DFT over n2 of the group k1
 #pragma unroll
-  for (int j = 0; j < ROWS; ++j) pr[j] = pi[j] = 0.0;
-  for (int m = wave; m < M; m += WAVES) {
-    const double zr = src[m * 2 * kHalf + i_re], zi = src[m * 2 * kHalf + i_im];
-    const int m1 = m >> 2;
+    for (int q = 0; q < 2; ++q) {
+      const int t = tid + 256 * q, m = t >> 3, k1 = t & 7;
+      if (m < M) {
+        double2* r = Z + m * kDp + 9 * k1;
+        double2 v[8];
 #pragma unroll
-    for (int j = 0; j < ROWS; ++j) {
-      const int t = (4 * m1 * j) & (kFft - 1);
-      const double cc = twt[2 * t], ss = twt[2 * t + 1];
-      pr[j] = fma(zr, cc, fma(zi, ss, pr[j]));
-      pi[j] = fma(zi, cc, fma(-zr, ss, pi[j]));
-    }
-  }
-  // combine Z[k1] = sum_m0 e^{-j 2 pi m0 k1 / 64} P_m0[k1 mod 16]; the rows of
-  // wavefront w have k1 mod 16 in [8 (w & 1), 8 (w & 1) + 8)
-  double zr_[ROWS], zi_[ROWS];
-  __syncthreads();  // every wavefront is done reading the row DFTs
+        for (int i = 0; i < 8; ++i) v[i] = r[i];
+        dft8(v);
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    if (h == 1) __syncthreads();  // half 0 consumed
-#pragma unroll
-    for (int jl = 0; jl < 8; ++jl) {
-      double* p = zx + ((wave * 8 + jl) * kFft + lane) * 2;
-      p[0] = pr[8 * h + jl];
-      p[1] = pi[8 * h + jl];
-    }
-    __syncthreads();
-    if ((wave & 1) == h) {
-#pragma unroll
-      for (int j = 0; j < ROWS; ++j) {
-        const int k1 = row_of<WAVES, true>(wave, j);
-        const int jl = (k1 & 15) - 8 * h;
-        double ar = 0.0, ai = 0.0;
-#pragma unroll
-        for (int m0 = 0; m0 < WAVES; ++m0) {
-          const double* p = zx + ((m0 * 8 + jl) * kFft + lane) * 2;
-          const double yr = p[0], yi = p[1];
-          const int t = (m0 * k1) & (kFft - 1);
-          const double cc = twt[2 * t], ss = twt[2 * t + 1];
-          ar = fma(yr, cc, fma(yi, ss, ar));
-          ai = fma(yi, cc, fma(-yr, ss, ai));
-        }
-        zr_[j] = ar;
-        zi_[j] = ai;
+        for (int i = 0; i < 8; ++i) r[i] = v[i];
       }
     }
-  }
-  // packed columns: their outputs for every row, for the mirrored reads
-  if (c == 0) {
+    __syncthreads();
+    // ---- columns: the same over the row index, one position per lane ----
 #pragma unroll
-    for (int j = 0; j < ROWS; ++j) {
-      const int k1 = row_of<WAVES, true>(wave, j);
-      pk[(part * kFft + k1) * 2] = zr_[j];
-      pk[(part * kFft + k1) * 2 + 1] = zi_[j];
-    }
-  }
-  __syncthreads();
-  double* dst = out + (part ? kSpecW : kSpecR0);
+    for (int q = 0; q < 2; ++q) {
+      const int m2 = wave + WAVES * q;
+      double2* c = Z + m2 * kDp + pp;
+      double2 v[8];
 #pragma unroll
-  for (int j = 0; j < ROWS; ++j) {
-    const int k1 = row_of<WAVES, true>(wave, j);
-    const int km = (kFft - k1) & (kFft - 1);
-    if (c != 0) {
-      dst[2 * (k1 * kFft + c)] = zr_[j];
-      dst[2 * (k1 * kFft + c) + 1] = zi_[j];
-      dst[2 * (km * kFft + kFft - c)] = zr_[j];
-      dst[2 * (km * kFft + kFft - c) + 1] = -zi_[j];
-    } else {
-      // P = A + j B with A, B the DFTs of the real columns 0 and 32:
-      // A = (P[k] + conj P[-k]) / 2, B = (P[k] - conj P[-k]) / (2 j)
-      const double qr = pk[(part * kFft + km) * 2], qi = pk[(part * kFft + km) * 2 + 1];
-      dst[2 * (k1 * kFft)] = 0.5 * (zr_[j] + qr);
-      dst[2 * (k1 * kFft) + 1] = 0.5 * (zi_[j] - qi);
-      dst[2 * (k1 * kFft + kFft / 2)] = 0.5 * (zi_[j] + qi);
-      dst[2 * (k1 * kFft + kFft / 2) + 1] = 0.5 * (qr - zr_[j]);
+      for (int i = 0; i < 8; ++i)
+        v[i] = 8 * i + m2 < M ? c[8 * i * kDp] : make_double2(0.0, 0.0);
+      dft8(v);
+#pragma unroll
+      for (int kk = 1; kk < 8; ++kk) v[kk] = dmul_conj(v[kk], tw[m2 * kk]);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) c[8 * i * kDp] = v[i];
     }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int k1 = wave + WAVES * q;
+      double2* c = Z + 8 * k1 * kDp + pp;
+      double2 v[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = c[i * kDp];
+      dft8(v);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) c[i * kDp] = v[i];
+    }
+    __syncthreads();
+
+    // ---- C: out, rows of the spectrum by wavefront ----
+    double2* o = reinterpret_cast<double2*>(out + (pass ? kSpecW : kSpecR0));
+    for (int k1 = wave; k1 < kFft; k1 += WAVES)
+      o[k1 * kFft + k2] = Z[(8 * (k1 & 7) + (k1 >> 3)) * kDp + c2];
+    __syncthreads();  // the grid is free for the next pass
   }
 }
 
@@ -1489,7 +1521,7 @@ hipError_t launch_dft64(const BlockArgs<float>& a, const double* radial64, int n
                         hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   static size_t attr_bytes = 0;
-  const size_t lds = (size_t)dft_layout(a.M, a.N, 4).total;
+  const size_t lds = kDftLdsBytes;
   return launch_with_lds(fse_dft64_kernel, attr_bytes, n_items, 256, lds, s, a, radial64);
 }
 
