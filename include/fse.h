@@ -413,7 +413,9 @@ typedef struct {
   int32_t frames, height, width;
   uint8_t *out;          /* same layout; may alias volume; known samples copied */
   double *out_f64;       /* nullable: unquantized result, same layout */
-  fse_stats *stats;      /* nullable: waves, lost blocks, largest wave */
+  fse_stats *stats;      /* nullable: waves, lost blocks, largest wave; latency_ms =
+                            device time from the first wave's launch to the
+                            8-bit output (HIP events; copies excluded) */
 } fse_volume;
 
 /* Create / destroy a 3-D plan (host buffers; work on the given HIP stream,

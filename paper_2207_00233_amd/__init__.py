@@ -524,7 +524,7 @@ class Plan3:
         v = _Volume(vol.ctypes.data, ls.ctypes.data, T, H, W, out.ctypes.data,
                     of.ctypes.data if of is not None else None, ctypes.pointer(st))
         _check(self._lib.fse_conceal_volume(self.handle, ctypes.byref(v)), "fse_conceal_volume")
-        return Result(out, of, st.waves, st.lost_blocks, st.max_wave_blocks)
+        return Result(out, of, st.waves, st.lost_blocks, st.max_wave_blocks, st.latency_ms)
 
 
 def schedule3(lost_blocks: np.ndarray, order: int = FSE_ORDER_OPTIMIZED):

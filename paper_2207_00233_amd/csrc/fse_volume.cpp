@@ -33,6 +33,7 @@ struct fse_plan3_s {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   DevBuf radial, twid, vol, lost, work, state, out, items, staging;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;  // device time of a call
   std::mutex mu;  // one call at a time
   int sticky = FSE_OK;
 };
@@ -116,6 +117,10 @@ int32_t fse_plan3(const fse_params3* p, void* hip_stream, fse_plan3_t* out) {
     fse_plan3_destroy(pl);
     return FSE_ERR_DEVICE;
   }
+  if (hipEventCreate(&pl->ev0) != hipSuccess || hipEventCreate(&pl->ev1) != hipSuccess) {
+    fse_plan3_destroy(pl);
+    return FSE_ERR_DEVICE;
+  }
   *out = pl;
   return FSE_OK;
 }
@@ -127,6 +132,8 @@ int32_t fse_plan3_destroy(fse_plan3_t pl) {
   for (DevBuf* b : {&pl->radial, &pl->twid, &pl->vol, &pl->lost, &pl->work, &pl->state, &pl->out,
                     &pl->items, &pl->staging})
     b->release();
+  if (pl->ev0) (void)hipEventDestroy(pl->ev0);
+  if (pl->ev1) (void)hipEventDestroy(pl->ev1);
   if (pl->own_stream && pl->stream) (void)hipStreamDestroy(pl->stream);
   delete pl;
   return FSE_OK;
@@ -211,6 +218,7 @@ int32_t fse_conceal_volume(fse_plan3_t pl, const fse_volume* v) {
   a.delta = p.delta;
   a.gamma = p.gamma;
   a.empty_fill = p.empty_fill;
+  if (hipEventRecord(pl->ev0, s) != hipSuccess) return fail(FSE_ERR_DEVICE);
   for (int w = 0; w < nwaves; ++w) {
     const int64_t i0 = wave_start[w], cnt = wave_start[w + 1] - i0;
     if (cnt <= 0) continue;
@@ -222,6 +230,7 @@ int32_t fse_conceal_volume(fse_plan3_t pl, const fse_volume* v) {
   if (launch_volume_finalize((const uint8_t*)pl->vol.ptr, (const uint8_t*)pl->state.ptr,
                              (const double*)pl->work.ptr, (uint8_t*)pl->out.ptr, n,
                              s) != hipSuccess ||
+      hipEventRecord(pl->ev1, s) != hipSuccess ||
       hipMemcpyAsync(v->out, pl->out.ptr, n, hipMemcpyDeviceToHost, s) != hipSuccess ||
       (v->out_f64 && hipMemcpyAsync(v->out_f64, pl->work.ptr, n * sizeof(double),
                                     hipMemcpyDeviceToHost, s) != hipSuccess) ||
@@ -232,7 +241,9 @@ int32_t fse_conceal_volume(fse_plan3_t pl, const fse_volume* v) {
     v->stats->lost_blocks = (int32_t)n_items;
     v->stats->max_wave_blocks = best;
     v->stats->reserved = 0;
-    v->stats->latency_ms = 0.0;
+    float ms = 0.f;
+    v->stats->latency_ms =
+        hipEventElapsedTime(&ms, pl->ev0, pl->ev1) == hipSuccess ? (double)ms : -1.0;
   }
   return FSE_OK;
 }
