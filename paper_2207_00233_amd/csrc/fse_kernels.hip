@@ -184,34 +184,57 @@ __device__ __forceinline__ unsigned umax3(unsigned a, unsigned b, unsigned c) {
   return max(a, max(b, c));
 }
 
-// Median of three (v_med3_u32).
+// Median of three as one v_med3_u32 (written out, the compiler splits some
+// of them into min/max pairs).
 __device__ __forceinline__ unsigned umed3(unsigned a, unsigned b, unsigned c) {
-  return max(min(a, b), min(max(a, b), c));
+  unsigned r;
+  asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
 }
 
-// Largest (m1) and second largest (m2) of N distinct keys: triples by
-// max3/med3, then merges, top2 of two pairs being med3(m1, n1, max(m2, n2)).
+// Largest (m1) and second largest (m2) of N distinct keys.  Triples give
+// (max3, med3); three (largest, second) pairs merge as largest = max3 of the
+// largest ones and second = max(med3 of the largest ones, max3 of the
+// seconds) (a loser's second is below the median of the largest ones); two
+// pairs as largest = max, second = med3(m, n, max of the seconds).  For 16
+// keys: 5 triples, two 3-way merges (the 16th key joins the second one),
+// one 2-way merge: 21 instructions.
 template <int N>
 __device__ __forceinline__ void top2(const unsigned (&k)[N], unsigned& m1, unsigned& m2) {
-  m1 = k[0];
-  m2 = 0u;
-  int j = 1;
-  if constexpr (N >= 3) {
-    m1 = umax3(k[0], k[1], k[2]);
-    m2 = umed3(k[0], k[1], k[2]);
-    j = 3;
-  }
+  if constexpr (N == 16) {
+    unsigned a[5], b[5];
 #pragma unroll
-  for (; j + 2 < N; j += 3) {
-    const unsigned n1 = umax3(k[j], k[j + 1], k[j + 2]);
-    const unsigned n2 = umed3(k[j], k[j + 1], k[j + 2]);
-    m2 = umed3(m1, n1, max(m2, n2));
-    m1 = max(m1, n1);
-  }
+    for (int t = 0; t < 5; ++t) {
+      a[t] = umax3(k[3 * t], k[3 * t + 1], k[3 * t + 2]);
+      b[t] = umed3(k[3 * t], k[3 * t + 1], k[3 * t + 2]);
+    }
+    const unsigned p1 = umax3(a[0], a[1], a[2]);
+    const unsigned q1 = max(umed3(a[0], a[1], a[2]), umax3(b[0], b[1], b[2]));
+    const unsigned p2 = umax3(a[3], a[4], k[15]);
+    const unsigned q2 = max(umed3(a[3], a[4], k[15]), max(b[3], b[4]));
+    m1 = max(p1, p2);
+    m2 = umed3(p1, p2, max(q1, q2));
+  } else {
+    m1 = k[0];
+    m2 = 0u;
+    int j = 1;
+    if constexpr (N >= 3) {
+      m1 = umax3(k[0], k[1], k[2]);
+      m2 = umed3(k[0], k[1], k[2]);
+      j = 3;
+    }
 #pragma unroll
-  for (; j < N; ++j) {
-    m2 = umed3(m1, k[j], m2);
-    m1 = max(m1, k[j]);
+    for (; j + 2 < N; j += 3) {
+      const unsigned n1 = umax3(k[j], k[j + 1], k[j + 2]);
+      const unsigned n2 = umed3(k[j], k[j + 1], k[j + 2]);
+      m2 = umed3(m1, n1, max(m2, n2));
+      m1 = max(m1, n1);
+    }
+#pragma unroll
+    for (; j < N; ++j) {
+      m2 = umed3(m1, k[j], m2);
+      m1 = max(m1, k[j]);
+    }
   }
 }
 

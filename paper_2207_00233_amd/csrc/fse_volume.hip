@@ -2,25 +2,34 @@
 // Selective Extrapolation for video volumes (the 3-D form the paper's
 // conclusion names), FP64.
 //
-// One workgroup of 256 threads extrapolates one lost block of a wave:
+// One workgroup of 512 threads (8 wavefronts, two per SIMD) extrapolates one
+// lost block of a wave:
 //   A  gather the Mt x M x N area (the block plus dt frames and d samples),
 //      classify and weight it (Eq. (2) with the 3-D distance), and place
 //      z = x + j s w (x = f w) at the first corner of the 8 x 32 x 32 grid in
-//      LDS, so that one complex transform gives both spectra;
-//   B  the 3-D DFT of z in place: along the columns (one thread per row of a
-//      frame), along the rows (one thread per column of a frame), along the
-//      frames (four lines of 8 per thread); then X = (Z[k] + conj Z[-k]) / 2
-//      into registers and W = (Z[k] - conj Z[-k]) / (2 j s) back into LDS;
+//      LDS (rows of 32 at a pitch of 33), so that one complex transform
+//      gives both spectra;
+//   B  the 3-D DFT of z in place: 32-point FFTs along the rows (one thread per
+//      row of a frame, the 32 values in registers, factorized as 8-point DFTs
+//      over n1 of z[4 n1 + n2], twiddles e^{-j 2 pi n2 k1 / 32}, 4-point DFTs
+//      over n2), the same along the columns (one thread per column), 8-point
+//      DFTs along the frames (two lines per thread); then
+//      X = (Z[k] + conj Z[-k]) / 2 into registers and
+//      W = (Z[k] - conj Z[-k]) / (2 j s) back into LDS;
 //   D  K greedy iterations: R[k] -= dc W[k - u] (indices mod 8, 32, 32),
 //      u = argmax |R|^2 (ties to the smallest (k1 32 + k2) 32 + k3),
-//      dc = gamma R[u] / W0;
+//      dc = gamma R[u] / W0: every thread scans its entries in increasing
+//      index order keeping the first largest, a wavefront takes the largest
+//      (exact double compare, ties by index), one slot per wavefront, one
+//      barrier, every lane reduces the eight slots;
 //   E  the model on the block's lost samples, sum_i Re(dc_i phi_{u_i}) with
 //      phi_k[t,m,n] = exp(+j 2 pi (4 k1 t + k2 m + k3 n) / 32) (the 8-point
 //      frame axis is every fourth point of the 32-point table), into a
 //      staging buffer that a second kernel applies after the wave, so every
 //      block of a wave reads the volume as it was at the wave's start.
-// Thread tid owns the 32 spectrum entries k3 = tid % 32, k2 = tid / 32 + 8q
-// (q = 0..3), k1 = 0..7.
+// Thread tid owns the 16 spectrum entries k3 = tid % 32 and (k1, k2) =
+// row r + 16 j of the 256 rows (k1 32 + k2), r = tid / 32, j = 0..15: k1 =
+// j / 2, k2 = r + 16 (j % 2).
 #include <hip/hip_runtime.h>
 
 #include "fse_device.h"
@@ -31,15 +40,83 @@ namespace fse {
 namespace {
 
 constexpr double kZScale = 128.0;  // balances x and w in z = x + j s w
+constexpr int kVWaves = kVThreads / 64;
 
 struct VSlot {  // a wavefront's best entry (32 bytes)
   double e, re, im;
   int k, pad;
 };
 
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) {
+  return make_double2(a.x + b.x, a.y + b.y);
+}
+__device__ __forceinline__ double2 csub(double2 a, double2 b) {
+  return make_double2(a.x - b.x, a.y - b.y);
+}
+// v e^{-j theta} with t = (cos theta, sin theta)
 __device__ __forceinline__ double2 cmul_conj(double2 v, double2 t) {
-  // v * conj(t) with t = (cos, sin): the forward-transform kernel e^{-j a}
   return make_double2(fma(v.x, t.x, v.y * t.y), fma(v.y, t.x, -v.x * t.y));
+}
+__device__ __forceinline__ double2 mul_mj(double2 v) { return make_double2(v.y, -v.x); }  // -j v
+
+// y[k] = sum_n x[n] e^{-j 2 pi n k / 4}, in place
+__device__ __forceinline__ void dft4(double2& x0, double2& x1, double2& x2, double2& x3) {
+  const double2 a = cadd(x0, x2), b = csub(x0, x2), c = cadd(x1, x3), d = mul_mj(csub(x1, x3));
+  x0 = cadd(a, c);
+  x2 = csub(a, c);
+  x1 = cadd(b, d);
+  x3 = csub(b, d);
+}
+
+// y[k] = sum_n x[n] e^{-j 2 pi n k / 8}, in place: 4-point DFTs of the even
+// and odd samples joined with the factors e^{-j 2 pi k / 8}
+__device__ __forceinline__ void dft8(double2 (&v)[8]) {
+  constexpr double c = 0.70710678118654752440;  // 1 / sqrt(2)
+  double2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  double2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4(e0, e1, e2, e3);
+  dft4(o0, o1, o2, o3);
+  o1 = make_double2(c * (o1.x + o1.y), c * (o1.y - o1.x));   // e^{-j pi / 4}
+  o2 = mul_mj(o2);                                           // e^{-j pi / 2}
+  o3 = make_double2(c * (o3.y - o3.x), -c * (o3.x + o3.y));  // e^{-j 3 pi / 4}
+  v[0] = cadd(e0, o0);
+  v[4] = csub(e0, o0);
+  v[1] = cadd(e1, o1);
+  v[5] = csub(e1, o1);
+  v[2] = cadd(e2, o2);
+  v[6] = csub(e2, o2);
+  v[3] = cadd(e3, o3);
+  v[7] = csub(e3, o3);
+}
+
+// 32-point DFT of the line at `p` with element stride `stride` (LDS), in
+// registers, written back in natural order; elements with index >= n_in are
+// taken as zero (not read).
+__device__ __forceinline__ void fft32_line(double2* p, int stride, int n_in, const double2* tw) {
+  double2 v[32];
+#pragma unroll
+  for (int i = 0; i < 32; ++i) v[i] = i < n_in ? p[i * stride] : make_double2(0.0, 0.0);
+  // position 4 k1 + n2 <- A[n2][k1] = DFT8 over n1 of v[4 n1 + n2], twiddled
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    double2 t[8];
+#pragma unroll
+    for (int n1 = 0; n1 < 8; ++n1) t[n1] = v[4 * n1 + n2];
+    dft8(t);
+#pragma unroll
+    for (int k1 = 0; k1 < 8; ++k1) v[4 * k1 + n2] = (n2 && k1) ? cmul_conj(t[k1], tw[n2 * k1]) : t[k1];
+  }
+  // position 4 k1 + k2 <- X[k1 + 8 k2] = DFT4 over n2
+#pragma unroll
+  for (int k1 = 0; k1 < 8; ++k1) dft4(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+#pragma unroll
+  for (int k = 0; k < 32; ++k) p[k * stride] = v[4 * (k & 7) + (k >> 3)];
+}
+
+__device__ __forceinline__ double read_lane_d(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
 }
 
 }  // namespace
@@ -47,7 +124,7 @@ __device__ __forceinline__ double2 cmul_conj(double2 v, double2 t) {
 __global__ __launch_bounds__(kVThreads, 1) void fse_volume_block_kernel(Vol3Args a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const Vol3Lds L = vol3_lds(a.K);
-  double2* Z = reinterpret_cast<double2*>(smem);  // [k1][k2][k3] (or [t][m][n])
+  double2* Z = reinterpret_cast<double2*>(smem);  // [t][m][n] / [k1][k2][k3], pitch kVPitch
   int* hu = reinterpret_cast<int*>(smem + L.hist_u);
   double2* hdc = reinterpret_cast<double2*>(smem + L.hist_dc);
   double2* tw = reinterpret_cast<double2*>(smem + L.tw);
@@ -60,7 +137,7 @@ __global__ __launch_bounds__(kVThreads, 1) void fse_volume_block_kernel(Vol3Args
   const int Mt = a.Mt, M = a.M, N = a.N, K = a.K;
 
   if (tid < 32) tw[tid] = make_double2(a.twid[2 * tid], a.twid[2 * tid + 1]);
-  for (int i = tid; i < kV3; i += kVThreads) Z[i] = make_double2(0.0, 0.0);
+  for (int i = tid; i < kVt * kVFrame; i += kVThreads) Z[i] = make_double2(0.0, 0.0);
   __syncthreads();
 
   // ---- A: gather, classify, weight ----
@@ -78,166 +155,140 @@ __global__ __launch_bounds__(kVThreads, 1) void fse_volume_block_kernel(Vol3Args
       f = a.work[p];
     }
     wsum += wv;
-    Z[(t * kVh + m) * kVw + n] = make_double2(f * wv, kZScale * wv);
+    Z[t * kVFrame + m * kVPitch + n] = make_double2(f * wv, kZScale * wv);
   }
   for (int off = 32; off >= 1; off >>= 1) wsum += __shfl_xor(wsum, off);
   if (lane == 0) red[wave] = wsum;
   __syncthreads();
   double W0 = 0.0;
 #pragma unroll
-  for (int q = 0; q < kVThreads / 64; ++q) W0 += red[q];
+  for (int q = 0; q < kVWaves; ++q) W0 += red[q];
 
-  const int g = tid >> 5, k3 = tid & 31;
+  const int k3 = tid & 31, r = tid >> 5;
   if (W0 > 0.0) {
     // ---- B: 3-D DFT in place ----
-    {  // columns n -> k3, one thread per row (t, m) = (g, k3)
-      const int t = g, m = k3;
-      if (t < Mt && m < M) {
-        double2 v[kVw];  // the row is in registers: results go straight back
-        double2* row = Z + (t * kVh + m) * kVw;
-#pragma unroll
-        for (int n = 0; n < kVw; ++n) v[n] = row[n];
-        for (int k = 0; k < kVw; ++k) {
-          double2 acc = make_double2(0.0, 0.0);
-#pragma unroll
-          for (int n = 0; n < kVw; ++n) {
-            const double2 c = cmul_conj(v[n], tw[(k * n) & 31]);
-            acc.x += c.x;
-            acc.y += c.y;
-          }
-          row[k] = acc;
-        }
-      }
+    if (tid < kVt * kVh) {  // rows: thread (t, m), 32-point DFT along n
+      const int t = tid >> 5, m = tid & 31;
+      if (t < Mt && m < M) fft32_line(Z + t * kVFrame + m * kVPitch, 1, N, tw);
     }
     __syncthreads();
-    {  // rows m -> k2, one thread per column (t, n) = (g, k3)
-      const int t = g, n = k3;
-      if (t < Mt) {
-        double2 v[kVh];
-#pragma unroll
-        for (int m = 0; m < kVh; ++m) v[m] = Z[(t * kVh + m) * kVw + n];
-        for (int k = 0; k < kVh; ++k) {
-          double2 acc = make_double2(0.0, 0.0);
-#pragma unroll
-          for (int m = 0; m < kVh; ++m) {
-            const double2 c = cmul_conj(v[m], tw[(k * m) & 31]);
-            acc.x += c.x;
-            acc.y += c.y;
-          }
-          Z[(t * kVh + k) * kVw + n] = acc;
-        }
-      }
+    if (tid < kVt * kVw) {  // columns: thread (t, n), 32-point DFT along m
+      const int t = tid >> 5, n = tid & 31;
+      if (t < Mt) fft32_line(Z + t * kVFrame + n, kVPitch, M, tw);
     }
     __syncthreads();
-    // frames t -> k1: lines (k2, k3), four per thread (frames >= Mt are 0)
-    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+    for (int q = 0; q < (kVh * kVw) / kVThreads; ++q) {  // frames: lines (m, n)
       const int line = tid + kVThreads * q;
-      double2 v[kVt], o[kVt];
+      double2* p = Z + (line >> 5) * kVPitch + (line & 31);
+      double2 v[8];
 #pragma unroll
-      for (int t = 0; t < kVt; ++t) v[t] = Z[t * kVh * kVw + line];
+      for (int t = 0; t < kVt; ++t) v[t] = t < Mt ? p[t * kVFrame] : make_double2(0.0, 0.0);
+      dft8(v);
 #pragma unroll
-      for (int k = 0; k < kVt; ++k) {
-        double2 acc = make_double2(0.0, 0.0);
-#pragma unroll
-        for (int t = 0; t < kVt; ++t) {
-          const double2 c = cmul_conj(v[t], tw[(4 * k * t) & 31]);
-          acc.x += c.x;
-          acc.y += c.y;
-        }
-        o[k] = acc;
-      }
-#pragma unroll
-      for (int k = 0; k < kVt; ++k) Z[k * kVh * kVw + line] = o[k];
+      for (int t = 0; t < kVt; ++t) p[t * kVFrame] = v[t];
     }
     __syncthreads();
   }
 
   // unpack: X into registers, W back into LDS
-  double rr[kVt][4], ri[kVt][4];
+  double rr[kVEnt], ri[kVEnt];
   if (W0 > 0.0) {
-    double wr[kVt][4], wi[kVt][4];
+    double wr[kVEnt], wi[kVEnt];
     const double h = 0.5, hs = 0.5 / kZScale;
 #pragma unroll
-    for (int k1 = 0; k1 < kVt; ++k1)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int k2 = g + 8 * q;
-        const double2 zk = Z[(k1 * kVh + k2) * kVw + k3];
-        const double2 zn = Z[((((kVt - k1) & 7) * kVh) + ((kVh - k2) & 31)) * kVw + ((kVw - k3) & 31)];
-        rr[k1][q] = h * (zk.x + zn.x);
-        ri[k1][q] = h * (zk.y - zn.y);
-        wr[k1][q] = hs * (zk.y + zn.y);
-        wi[k1][q] = hs * (zn.x - zk.x);
-      }
+    for (int j = 0; j < kVEnt; ++j) {
+      const int k1 = j >> 1, k2 = r + 16 * (j & 1);
+      const double2 zk = Z[k1 * kVFrame + k2 * kVPitch + k3];
+      const double2 zn =
+          Z[((kVt - k1) & 7) * kVFrame + ((kVh - k2) & 31) * kVPitch + ((kVw - k3) & 31)];
+      rr[j] = h * (zk.x + zn.x);
+      ri[j] = h * (zk.y - zn.y);
+      wr[j] = hs * (zk.y + zn.y);
+      wi[j] = hs * (zn.x - zk.x);
+    }
     __syncthreads();
 #pragma unroll
-    for (int k1 = 0; k1 < kVt; ++k1)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) Z[(k1 * kVh + g + 8 * q) * kVw + k3] = make_double2(wr[k1][q], wi[k1][q]);
+    for (int j = 0; j < kVEnt; ++j)
+      Z[(j >> 1) * kVFrame + (r + 16 * (j & 1)) * kVPitch + k3] = make_double2(wr[j], wi[j]);
     __syncthreads();
 
     // ---- D: K greedy iterations ----
     const double gs = a.gamma / W0;
+    const int kbase = r * 32 + k3;  // index of entry j: kbase + 512 j
     int u = 0;
     double dcr = 0.0, dci = 0.0;
     for (int it = 0; it < K; ++it) {
       const int u1 = u >> 10, u2 = (u >> 5) & 31, u3 = u & 31;
       const int c3 = (k3 - u3) & 31;
-      double be = -1.0, bre = 0.0, bim = 0.0;
-      int bk = 0;
+      const int a0 = ((r - u2) & 31) * kVPitch + c3, a1 = ((r + 16 - u2) & 31) * kVPitch + c3;
+      double be = -1.0;
+      int bjx = 0;
 #pragma unroll
-      for (int k1 = 0; k1 < kVt; ++k1) {
-        const int p1 = ((k1 - u1) & 7) * (kVh * kVw);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int k2 = g + 8 * q;
-          const double2 w = Z[p1 + ((k2 - u2) & 31) * kVw + c3];
-          double r = rr[k1][q], s = ri[k1][q];
-          r = fma(-dcr, w.x, fma(dci, w.y, r));
-          s = fma(-dcr, w.y, fma(-dci, w.x, s));
-          rr[k1][q] = r;
-          ri[k1][q] = s;
-          const double e = fma(r, r, s * s);
-          if (e > be) {  // entries in increasing index order: the first maximum stays
-            be = e;
-            bre = r;
-            bim = s;
-            bk = (k1 * kVh + k2) * kVw + k3;
-          }
+      for (int j = 0; j < kVEnt; ++j) {
+        const int k1 = j >> 1;
+        const double2 w = Z[((k1 - u1) & 7) * kVFrame + ((j & 1) ? a1 : a0)];
+        double x = rr[j], y = ri[j];
+        x = fma(-dcr, w.x, fma(dci, w.y, x));
+        y = fma(-dcr, w.y, fma(-dci, w.x, y));
+        rr[j] = x;
+        ri[j] = y;
+        const double e = fma(x, x, y * y);
+        if (e > be) {  // increasing index order: the first maximum stays
+          be = e;
+          bjx = j;
         }
       }
       // wavefront: the largest |R|^2, ties to the smallest index
-      for (int off = 32; off >= 1; off >>= 1) {
-        const double oe = __shfl_xor(be, off), ore = __shfl_xor(bre, off),
-                     oim = __shfl_xor(bim, off);
-        const int ok = __shfl_xor(bk, off);
-        if (oe > be || (oe == be && ok < bk)) {
-          be = oe;
-          bre = ore;
-          bim = oim;
-          bk = ok;
-        }
+      double gm = be;
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) gm = fmax(gm, __shfl_xor(gm, off));
+      const unsigned long long hit = __ballot(be == gm);
+      int lw = __builtin_ctzll(hit);
+      if (__builtin_popcountll(hit) > 1) {  // exact ties between lanes
+        int kk = be == gm ? kbase + 512 * bjx : 0x7fffffff;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) kk = min(kk, __shfl_xor(kk, off));
+        lw = __builtin_ctzll(__ballot(be == gm && kbase + 512 * bjx == kk));
       }
-      VSlot* sl = slots + (it & 1) * (kVThreads / 64);
-      if (lane == 0) {
+      lw = __builtin_amdgcn_readfirstlane(lw);
+      const int jw = __builtin_amdgcn_readfirstlane(__builtin_amdgcn_readlane(bjx, lw));
+      double sx = rr[0], sy = ri[0];
+#pragma unroll
+      for (int j = 1; j < kVEnt; ++j)
+        if (j == jw) {
+          sx = rr[j];
+          sy = ri[j];
+        }
+      VSlot* sl = slots + (it & 1) * kVWaves;
+      if (lane == lw) {
         VSlot v;
         v.e = be;
-        v.re = bre;
-        v.im = bim;
-        v.k = bk;
+        v.re = sx;
+        v.im = sy;
+        v.k = kbase + 512 * jw;
         v.pad = 0;
         sl[wave] = v;
       }
       __syncthreads();
-      VSlot best = sl[0];
+      // block: lanes of a group of 8 reduce the 8 slots
+      const VSlot mine = sl[lane & 7];
+      double ge = mine.e;
+      int gk = (mine.k << 3) | (lane & 7);
 #pragma unroll
-      for (int q = 1; q < kVThreads / 64; ++q) {
-        const VSlot c = sl[q];
-        if (c.e > best.e || (c.e == best.e && c.k < best.k)) best = c;
+      for (int off = 1; off < kVWaves; off <<= 1) {
+        const double oe = __shfl_xor(ge, off);
+        const int ok = __shfl_xor(gk, off);
+        if (oe > ge || (oe == ge && ok < gk)) {
+          ge = oe;
+          gk = ok;
+        }
       }
-      u = __builtin_amdgcn_readfirstlane(best.k);
-      dcr = gs * best.re;
-      dci = gs * best.im;
+      gk = __builtin_amdgcn_readfirstlane(gk);
+      u = gk >> 3;
+      const VSlot& win = sl[gk & 7];
+      dcr = gs * win.re;
+      dci = gs * win.im;
       if (tid == 0) {
         hu[it] = u;
         hdc[it] = make_double2(dcr, dci);
