@@ -222,8 +222,7 @@ __global__ __launch_bounds__(kVThreads, 1) void fse_volume_block_kernel(Vol3Args
       const int u1 = u >> 10, u2 = (u >> 5) & 31, u3 = u & 31;
       const int c3 = (k3 - u3) & 31;
       const int a0 = ((r - u2) & 31) * kVPitch + c3, a1 = ((r + 16 - u2) & 31) * kVPitch + c3;
-      double be = -1.0;
-      int bjx = 0;
+      double e[kVEnt];
 #pragma unroll
       for (int j = 0; j < kVEnt; ++j) {
         const int k1 = j >> 1;
@@ -233,33 +232,29 @@ __global__ __launch_bounds__(kVThreads, 1) void fse_volume_block_kernel(Vol3Args
         y = fma(-dcr, w.y, fma(-dci, w.x, y));
         rr[j] = x;
         ri[j] = y;
-        const double e = fma(x, x, y * y);
-        if (e > be) {  // increasing index order: the first maximum stays
-          be = e;
-          bjx = j;
-        }
+        e[j] = fma(x, x, y * y);
       }
-      // wavefront: the largest |R|^2, ties to the smallest index
+      double be = e[0];
+#pragma unroll
+      for (int j = 1; j < kVEnt; ++j) be = fmax(be, e[j]);
+      // wavefront: the largest |R|^2; the entry holding it is the lowest
+      // entry index j, then the lowest lane, among those equal to it (for
+      // equal values the smallest index (k1 32 + k2) 32 + k3 = kbase + 512 j)
       double gm = be;
 #pragma unroll
       for (int off = 32; off >= 1; off >>= 1) gm = fmax(gm, __shfl_xor(gm, off));
-      const unsigned long long hit = __ballot(be == gm);
-      int lw = __builtin_ctzll(hit);
-      if (__builtin_popcountll(hit) > 1) {  // exact ties between lanes
-        int kk = be == gm ? kbase + 512 * bjx : 0x7fffffff;
+      int jw = kVEnt, lw = 0;
 #pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) kk = min(kk, __shfl_xor(kk, off));
-        lw = __builtin_ctzll(__ballot(be == gm && kbase + 512 * bjx == kk));
-      }
-      lw = __builtin_amdgcn_readfirstlane(lw);
-      const int jw = __builtin_amdgcn_readfirstlane(__builtin_amdgcn_readlane(bjx, lw));
-      double sx = rr[0], sy = ri[0];
-#pragma unroll
-      for (int j = 1; j < kVEnt; ++j)
-        if (j == jw) {
-          sx = rr[j];
-          sy = ri[j];
+      for (int j = kVEnt - 1; j >= 0; --j) {  // lowest j wins
+        const unsigned long long m = __ballot(e[j] == gm);
+        if (m) {
+          jw = j;
+          lw = __builtin_ctzll(m);
         }
+      }
+      jw = __builtin_amdgcn_readfirstlane(jw);
+      lw = __builtin_amdgcn_readfirstlane(lw);
+      const double sx = rr[jw], sy = ri[jw];  // uniform register index
       VSlot* sl = slots + (it & 1) * kVWaves;
       if (lane == lw) {
         VSlot v;
