@@ -113,6 +113,21 @@ __device__ __forceinline__ void fft32_line(double2* p, int stride, int n_in, con
   for (int k = 0; k < 32; ++k) p[k * stride] = v[4 * (k & 7) + (k >> 3)];
 }
 
+// One DPP step of a maximum in double: x = max(x, x moved by CTRL); lanes
+// without a source (or outside ROWS) keep their own value.
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ double dpp_fmax(double x) {
+  const int lo = __double2loint(x), hi = __double2hiint(x);
+  const int ylo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWS, 0xF, false);
+  const int yhi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWS, 0xF, false);
+  return fmax(x, __hiloint2double(yhi, ylo));
+}
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_imin(int x) {
+  return min(x, __builtin_amdgcn_update_dpp(x, x, CTRL, 0xF, 0xF, false));
+}
+
 __device__ __forceinline__ double read_lane_d(double v, int l) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
@@ -240,9 +255,15 @@ __global__ __launch_bounds__(kVThreads, 1) void fse_volume_block_kernel(Vol3Args
       // wavefront: the largest |R|^2; the entry holding it is the lowest
       // entry index j, then the lowest lane, among those equal to it (for
       // equal values the smallest index (k1 32 + k2) 32 + k3 = kbase + 512 j)
-      double gm = be;
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) gm = fmax(gm, __shfl_xor(gm, off));
+      // quads, rows of 16, then rows 1 and 3 (row_bcast:15), row 3
+      // (row_bcast:31): lane 63 holds the wavefront's maximum
+      double gm = dpp_fmax<0xB1>(be);  // quad_perm [1,0,3,2]
+      gm = dpp_fmax<0x4E>(gm);         // quad_perm [2,3,0,1]
+      gm = dpp_fmax<0x124>(gm);        // row_ror:4
+      gm = dpp_fmax<0x128>(gm);        // row_ror:8
+      gm = dpp_fmax<0x142, 0xA>(gm);   // row_bcast:15
+      gm = dpp_fmax<0x143, 0xC>(gm);   // row_bcast:31
+      gm = read_lane_d(gm, 63);
       int jw = kVEnt, lw = 0;
 #pragma unroll
       for (int j = kVEnt - 1; j >= 0; --j) {  // lowest j wins
@@ -266,19 +287,17 @@ __global__ __launch_bounds__(kVThreads, 1) void fse_volume_block_kernel(Vol3Args
         sl[wave] = v;
       }
       __syncthreads();
-      // block: lanes of a group of 8 reduce the 8 slots
+      // block: lane l reads slot l % 8 (the data repeat with period 8, so
+      // quad and row-of-8 DPP steps reduce all eight): the largest |R|^2, then
+      // the smallest index among the slots holding it
       const VSlot mine = sl[lane & 7];
-      double ge = mine.e;
-      int gk = (mine.k << 3) | (lane & 7);
-#pragma unroll
-      for (int off = 1; off < kVWaves; off <<= 1) {
-        const double oe = __shfl_xor(ge, off);
-        const int ok = __shfl_xor(gk, off);
-        if (oe > ge || (oe == ge && ok < gk)) {
-          ge = oe;
-          gk = ok;
-        }
-      }
+      double ge = dpp_fmax<0xB1>(mine.e);  // quad_perm [1,0,3,2]
+      ge = dpp_fmax<0x4E>(ge);             // quad_perm [2,3,0,1]
+      ge = dpp_fmax<0x124>(ge);            // row_ror:4
+      int gk = mine.e == ge ? (mine.k << 3) | (lane & 7) : 0x7fffffff;
+      gk = dpp_imin<0xB1>(gk);
+      gk = dpp_imin<0x4E>(gk);
+      gk = dpp_imin<0x124>(gk);
       gk = __builtin_amdgcn_readfirstlane(gk);
       u = gk >> 3;
       const VSlot& win = sl[gk & 7];
