@@ -2,6 +2,7 @@
 declared in include/fse.h, validates parameters before touching a device, and
 its host scheduler agrees with the oracle's independent one."""
 import ctypes
+import dataclasses
 import os
 import re
 
@@ -142,3 +143,24 @@ def test_host_refined_scheduler_large_grid(lib):
     assert a[0] == b[0] and a[0] > 0
     np.testing.assert_array_equal(a[1], b[1])
     np.testing.assert_array_equal(a[2], b[2])
+
+
+def test_volume_entry_points_validate_before_touching_the_device(lib):
+    # fse_plan3 checks its parameters before any HIP call, so these return
+    # the documented codes on a machine without a GPU as well
+    ok = fse.Params3()
+    assert lib.fse_plan3(None, None, ctypes.byref(ctypes.c_void_p())) == fse.FSE_ERR_INVALID
+    assert lib.fse_plan3(ctypes.byref(ok.c()), None, None) == fse.FSE_ERR_INVALID
+    for bad, code in ((dict(block_h=0), fse.FSE_ERR_INVALID),
+                      (dict(rho=0.0), fse.FSE_ERR_INVALID),
+                      (dict(iterations=0), fse.FSE_ERR_INVALID),
+                      (dict(order=fse.FSE_ORDER_REFINED), fse.FSE_ERR_INVALID),
+                      (dict(block_h=20), fse.FSE_ERR_INVALID),          # 20 + 2 * 8 > 32
+                      (dict(fft_h=64, fft_w=64), fse.FSE_ERR_UNSUPPORTED),
+                      (dict(precision=fse.FSE_FP32), fse.FSE_ERR_UNSUPPORTED)):
+        pc = dataclasses.replace(ok, **bad).c()
+        h = ctypes.c_void_p()
+        assert lib.fse_plan3(ctypes.byref(pc), None, ctypes.byref(h)) == code, bad
+        assert not h.value
+    assert lib.fse_plan3_destroy(None) == fse.FSE_OK
+    assert lib.fse_conceal_volume(None, None) == fse.FSE_ERR_INVALID

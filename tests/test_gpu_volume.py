@@ -125,3 +125,15 @@ def test_volume_full_size_sampled_blocks_teacher_forced():
         worst = max(worst, err)
         assert err <= FP64_TOL * 255, (int(b), int(w), err)
     print(f"[gpu] 3-D full size: {len(picks)} blocks, worst {worst:.2e}", flush=True)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(border_t=0, iterations=30),                      # one-frame areas on the 8-frame grid
+    dict(iterations=1),                                   # a single iteration
+    dict(rho=1.0, delta=0.0, iterations=40),              # flat weights, reconstructed samples unused
+    dict(block_t=4, block_h=4, block_w=4, border_t=1, border_d=4, iterations=40),  # 6 x 12 x 12 areas
+    dict(block_t=1, block_h=8, block_w=16, border_t=3, border_d=7, iterations=40),  # 7 x 22 x 30
+])
+def test_volume_parameter_edges(kw):
+    v = synth.video_volume(seed=4, frames=7, height=40, width=56, block=8, p=0.25)
+    _check(fse.Params3(**kw), v.volume, v.lost)
