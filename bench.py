@@ -73,9 +73,9 @@ def measured_record(precision):
 
 
 def measured_traffic(precision):
-    """HBM bytes of the block kernel per step (see measured_record), or None."""
+    """HBM bytes of the block kernel per launch (see measured_record), or None."""
     rec = measured_record(precision)
-    return rec["traffic_bytes_per_step"] if rec else None
+    return rec["traffic_bytes_per_launch"] if rec else None
 
 
 def log(*a):
@@ -493,9 +493,17 @@ def main():
               else FLOPS_PER_BLOCK)
     # launches of different frame groups overlap: the kernel's flops over the
     # time at least one of its launches ran (union of the launch intervals)
+    # per launch: the algorithmic flops of the blocks one launch processes
+    # (on average) over the kernel's average launch duration (HIP events on
+    # the launch's own stream)
+    achieved = kflops * blocks_per_launch / (avg_launch_ms * 1e-3) / 1e12
+    # the frame groups' launches overlap, so a launch's duration includes the
+    # time it shares the GPU: also the step's flops over the union of the
+    # kernel's launch intervals
     busy_ms = head["kernel_busy_ms_per_step"]
-    achieved = kflops * lost_blocks / (busy_ms * 1e-3) / 1e12
+    achieved_union = kflops * lost_blocks / (busy_ms * 1e-3) / 1e12
     traffic = measured_traffic(args.precision)
+    alg_bytes_launch = ALG_HBM_BYTES_PER_BLOCK * blocks_per_launch
     # VALU issue: the committed SQ_INSTS_VALU count of a step over the
     # kernel's busy time, against what 1024 SIMDs issue (a wave64 VALU
     # instruction occupies a 16-lane SIMD for 4 cycles)
@@ -605,24 +613,32 @@ def main():
                    "hip_hw_queues": int(os.environ["GPU_MAX_HW_QUEUES"])},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_PUBLISHED,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_PUBLISHED, "traffic": traffic,
+                     "kernel": "fse_block_kernel<float>",
+                     "flops_per_block": kflops, "blocks_per_launch": blocks_per_launch,
+                     "avg_launch_ms": avg_launch_ms,
+                     "achieved_note": "algorithmic flops of the blocks one launch processes on "
+                                      "average over the kernel's average launch duration (HIP "
+                                      "events on the launch's stream)",
                      "peak_nonpacked": PEAK_FP32_TFLOPS,
                      "frac_nonpacked": achieved / PEAK_FP32_TFLOPS,
                      "peak_note": "published FP32 vector peak (counts packed FP32); this "
                                   "build compiles without packed FP32 instructions, so "
                                   "78.6 TFLOP/s (256 CU x 4 SIMD x 16 lanes x FMA x "
                                   "2.4 GHz) is what it can issue",
-                     "algorithmic_hbm_bytes_per_step": ALG_HBM_BYTES_PER_BLOCK * lost_blocks,
-                     "traffic_over_algorithmic": (traffic / (ALG_HBM_BYTES_PER_BLOCK * lost_blocks)
-                                                  if traffic else None),
-                     "kernel": "fse_block_kernel<float>",
-                     "avg_launch_ms": avg_launch_ms, "blocks_per_launch": blocks_per_launch,
+                     "achieved_union": achieved_union,
+                     "frac_union": achieved_union / PEAK_FP32_PUBLISHED,
+                     "frac_union_nonpacked": achieved_union / PEAK_FP32_TFLOPS,
                      "kernel_busy_ms_per_step": busy_ms, "groups": head["groups"],
-                     "flops_per_block": kflops,
-                     "achieved_note": "flops of all blocks of a step over the union of the "
-                                      "kernel's launch intervals (HIP events), since launches "
-                                      "of different frame groups overlap",
-                     "traffic_note": "HBM bytes of the kernel per step (all launches) from "
-                                     "rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0 (copy-"
+                     "union_note": "the frame groups' launches overlap (summed launch time "
+                                   "over the union of the launch intervals: the overlap "
+                                   "factor), so a launch's duration includes the time it "
+                                   "shares the GPU; achieved_union = the step's flops over "
+                                   "the union of the kernel's launch intervals",
+                     "overlap_factor": avg_launch_ms * launches / args.steps / busy_ms,
+                     "algorithmic_hbm_bytes_per_launch": alg_bytes_launch,
+                     "traffic_over_algorithmic": (traffic / alg_bytes_launch if traffic else None),
+                     "traffic_note": "HBM bytes of one launch on average (the step's launches) "
+                                     "from rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0 (copy-"
                                      "calibrated), taken on this kernel source and launch "
                                      "configuration; null when either changed since",
                      "valu_issue_frac": valu_issue_frac,
