@@ -493,15 +493,14 @@ def main():
               else FLOPS_PER_BLOCK)
     # launches of different frame groups overlap: the kernel's flops over the
     # time at least one of its launches ran (union of the launch intervals)
-    # per launch: the algorithmic flops of the blocks one launch processes
-    # (on average) over the kernel's average launch duration (HIP events on
-    # the launch's own stream)
-    achieved = kflops * blocks_per_launch / (avg_launch_ms * 1e-3) / 1e12
     # the frame groups' launches overlap, so a launch's duration includes the
-    # time it shares the GPU: also the step's flops over the union of the
-    # kernel's launch intervals
+    # time it shares the GPU: achieved = the step's flops over the union of
+    # the kernel's launch intervals (HIP events on the launches' own streams);
+    # beside it the per-launch figure: the flops of the blocks one launch
+    # processes on average over the average launch duration
     busy_ms = head["kernel_busy_ms_per_step"]
-    achieved_union = kflops * lost_blocks / (busy_ms * 1e-3) / 1e12
+    achieved = kflops * lost_blocks / (busy_ms * 1e-3) / 1e12
+    achieved_launch = kflops * blocks_per_launch / (avg_launch_ms * 1e-3) / 1e12
     traffic = measured_traffic(args.precision)
     alg_bytes_launch = ALG_HBM_BYTES_PER_BLOCK * blocks_per_launch
     # VALU issue: the committed SQ_INSTS_VALU count of a step over the
@@ -616,24 +615,24 @@ def main():
                      "kernel": "fse_block_kernel<float>",
                      "flops_per_block": kflops, "blocks_per_launch": blocks_per_launch,
                      "avg_launch_ms": avg_launch_ms,
-                     "achieved_note": "algorithmic flops of the blocks one launch processes on "
-                                      "average over the kernel's average launch duration (HIP "
-                                      "events on the launch's stream)",
+                     "achieved_note": "algorithmic flops of all blocks of a step over the "
+                                      "union of the kernel's launch intervals (HIP events on "
+                                      "the launches' streams): the launches of the frame "
+                                      "groups overlap",
                      "peak_nonpacked": PEAK_FP32_TFLOPS,
                      "frac_nonpacked": achieved / PEAK_FP32_TFLOPS,
                      "peak_note": "published FP32 vector peak (counts packed FP32); this "
                                   "build compiles without packed FP32 instructions, so "
                                   "78.6 TFLOP/s (256 CU x 4 SIMD x 16 lanes x FMA x "
                                   "2.4 GHz) is what it can issue",
-                     "achieved_union": achieved_union,
-                     "frac_union": achieved_union / PEAK_FP32_PUBLISHED,
-                     "frac_union_nonpacked": achieved_union / PEAK_FP32_TFLOPS,
                      "kernel_busy_ms_per_step": busy_ms, "groups": head["groups"],
-                     "union_note": "the frame groups' launches overlap (summed launch time "
-                                   "over the union of the launch intervals: the overlap "
-                                   "factor), so a launch's duration includes the time it "
-                                   "shares the GPU; achieved_union = the step's flops over "
-                                   "the union of the kernel's launch intervals",
+                     "achieved_per_launch": achieved_launch,
+                     "frac_per_launch": achieved_launch / PEAK_FP32_PUBLISHED,
+                     "per_launch_note": "the flops of the blocks one launch processes on "
+                                        "average over the average launch duration; a launch "
+                                        "shares the GPU with the other groups' launches "
+                                        "(overlap_factor = summed launch time over the union "
+                                        "of the launch intervals)",
                      "overlap_factor": avg_launch_ms * launches / args.steps / busy_ms,
                      "algorithmic_hbm_bytes_per_launch": alg_bytes_launch,
                      "traffic_over_algorithmic": (traffic / alg_bytes_launch if traffic else None),
