@@ -274,8 +274,9 @@ int32_t fse_plan_serving_stats(fse_plan_t plan, fse_serving_stats *out);
 /*
  * Processing order only (paper Algorithm 1 / line scan) for a block grid of
  * hb x wb blocks; lost[hb*wb] nonzero marks blocks with samples to
- * extrapolate (FSE_ORDER_REFINED needs sample counts: fse_schedule_refined).  wave_of[hb*wb] receives the wave index (-1 for the other
- * blocks); seq[hb*wb] (nullable) the lost blocks in processing order.
+ * extrapolate (FSE_ORDER_REFINED needs sample counts: fse_schedule_refined).
+ * wave_of[hb*wb] receives the wave index (-1 for the other blocks);
+ * seq[hb*wb] (nullable) the lost blocks in processing order.
  * Host-only; returns the number of waves (>= 0) or FSE_ERR_INVALID.
  */
 int32_t fse_schedule(int32_t hb, int32_t wb, const uint8_t *lost, int32_t order,
@@ -426,8 +427,12 @@ int32_t fse_plan3(const fse_params3 *p, void *hip_stream, fse_plan3_t *out);
 int32_t fse_plan3_destroy(fse_plan3_t plan);
 
 /* Conceal one volume synchronously (host pointers; the call returns with the
- * result in `out`).  Errors: FSE_ERR_INVALID (null pointers, sizes <= 0 or
- * above 65535 per dimension), FSE_ERR_DEVICE. */
+ * result in `out`).  Device memory: about 13 bytes per sample plus the
+ * staging of the largest wave, kept by the plan for later calls.  Errors:
+ * FSE_ERR_INVALID (null pointers, sizes <= 0 or above 65535 per dimension),
+ * FSE_ERR_NOMEM (the device buffers could not be allocated; the plan stays
+ * usable), FSE_ERR_DEVICE (a HIP call failed; the plan reports it from then
+ * on). */
 int32_t fse_conceal_volume(fse_plan3_t plan, const fse_volume *v);
 
 /* Processing order only, for a tb x hb x wb block grid (frame-major);

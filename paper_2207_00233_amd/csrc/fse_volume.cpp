@@ -188,8 +188,10 @@ int32_t fse_conceal_volume(fse_plan3_t pl, const fse_volume* v) {
   if (pl->vol.reserve(n) || pl->lost.reserve(n) || pl->work.reserve(n * sizeof(double)) ||
       pl->state.reserve(n) || pl->out.reserve(n) ||
       pl->items.reserve(items.size() * sizeof(int32_t)) ||
-      pl->staging.reserve((size_t)std::max(1, best) * blk * sizeof(double)))
-    return fail(FSE_ERR_DEVICE);
+      pl->staging.reserve((size_t)std::max(1, best) * blk * sizeof(double))) {
+    (void)hipGetLastError();  // an allocation that failed leaves the plan usable
+    return FSE_ERR_NOMEM;
+  }
   if (hipMemcpyAsync(pl->vol.ptr, v->volume, n, hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(pl->lost.ptr, v->lost, n, hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(pl->items.ptr, items.data(), items.size() * sizeof(int32_t),
