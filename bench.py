@@ -40,6 +40,9 @@ PEAK_FP32_PUBLISHED = 157.3  # MI355X's published FP32 vector peak (packed FP32)
 # The method's own HBM bytes per lost block: the 44 x 44 area read (float
 # sample + state byte) and the 16 x 16 block written back (float + state).
 ALG_HBM_BYTES_PER_BLOCK = (BLOCK + 2 * BORDER) ** 2 * 5 + BLOCK * BLOCK * 5
+# LDS bytes of the shifted read of W per lost block: K iterations x 4096
+# entries x 8 bytes (float complex)
+LDS_BYTES_PER_BLOCK = K_ITER * 4096 * 8
 # whether a precision mode meets the parity bar (0.5 max-abs on every block,
 # teacher-forced; tests/test_gpu_precision_sweep.py)
 MEETS_BAR = {"fp64": True, "fp32_rerank": True, "fp32": False, "fp32_f16x3": False}
@@ -391,6 +394,7 @@ def main():
     ap.add_argument("--no-order", action="store_true")
     ap.add_argument("--no-e2e", action="store_true")
     ap.add_argument("--no-volume", action="store_true")
+    ap.add_argument("--no-peaks", action="store_true")
     ap.add_argument("--precision", choices=("fp32", "fp32_rerank", "fp32_f16x3"), default="fp32_rerank",
                     help="arithmetic of the headline batched run")
     ap.add_argument("--seed", type=int, default=0)
@@ -503,6 +507,16 @@ def main():
     achieved_launch = kflops * blocks_per_launch / (avg_launch_ms * 1e-3) / 1e12
     traffic = measured_traffic(args.precision)
     alg_bytes_launch = ALG_HBM_BYTES_PER_BLOCK * blocks_per_launch
+    # the shifted read of W is the iteration's LDS traffic: 8 bytes (float
+    # complex) per spectrum entry and iteration
+    lds_tbps = LDS_BYTES_PER_BLOCK * lost_blocks / (busy_ms * 1e-3) / 1e12
+    peaks = None
+    if not args.no_peaks:
+        log("[bench] measured peaks (FMA, LDS, HBM microbenchmarks)")
+        peaks = fse.measure_peaks()
+        log(f"[bench] peaks: FP32 FMA {peaks['fp32_fma_tflops']:.1f} TFLOP/s, FP64 FMA "
+            f"{peaks['fp64_fma_tflops']:.1f}, LDS {peaks['lds_read_tbps']:.1f} TB/s, HBM copy "
+            f"{peaks['hbm_copy_tbps']:.2f} TB/s")
     # VALU issue: the committed SQ_INSTS_VALU count of a step over the
     # kernel's busy time, against what 1024 SIMDs issue (a wave64 VALU
     # instruction occupies a 16-lane SIMD for 4 cycles)
@@ -640,6 +654,15 @@ def main():
                                      "from rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0 (copy-"
                                      "calibrated), taken on this kernel source and launch "
                                      "configuration; null when either changed since",
+                     "measured_peaks": peaks,
+                     "frac_of_measured_fp32_fma": (achieved / peaks["fp32_fma_tflops"]
+                                                   if peaks else None),
+                     "lds_tbps": lds_tbps,
+                     "lds_frac_of_measured": (lds_tbps / peaks["lds_read_tbps"]
+                                              if peaks else None),
+                     "lds_note": "the iteration's shifted reads of W (K x 4096 x 8 bytes per "
+                                 "block) over the kernel's busy time, against the measured "
+                                 "LDS read bandwidth",
                      "valu_issue_frac": valu_issue_frac,
                      "valu_issue_note": "VALU wavefront-instructions of a step (rocprofv3 "
                                         "SQ_INSTS_VALU, same source and launch configuration; "

@@ -42,7 +42,7 @@ EXPORTED = ("fse_plan", "fse_plan_destroy", "fse_conceal_image", "fse_conceal_im
             "fse_submit", "fse_poll", "fse_schedule", "fse_schedule_refined",
             "fse_last_call_stats", "fse_plan_get_tuning", "fse_plan_set_tuning",
             "fse_plan_serving_stats", "fse_plan3", "fse_plan3_destroy", "fse_conceal_volume",
-            "fse_schedule3", "fse_strerror")
+            "fse_schedule3", "fse_measure_peaks", "fse_strerror")
 FSE_NOALLOC_SCRATCH_BYTES = 128 << 20
 
 
@@ -103,6 +103,20 @@ class _ServingStats(ctypes.Structure):
                 ("peak_committed", ctypes.c_int64), ("admitted_frames", ctypes.c_int64),
                 ("peak_frames", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("step_blocks_cap", ctypes.c_int64), ("peak_step_blocks", ctypes.c_int64)]
+
+
+class _Peaks(ctypes.Structure):
+    _fields_ = [("fp32_fma_tflops", ctypes.c_double), ("fp64_fma_tflops", ctypes.c_double),
+                ("lds_read_tbps", ctypes.c_double), ("hbm_copy_tbps", ctypes.c_double),
+                ("compute_units", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+def measure_peaks() -> dict:
+    """fse_measure_peaks: the current device's measured FP32 / FP64 vector FMA
+    rates (TFLOP/s), LDS read and HBM copy bandwidths (TB/s)."""
+    pk = _Peaks()
+    _check(load().fse_measure_peaks(ctypes.byref(pk)), "fse_measure_peaks")
+    return {k: getattr(pk, k) for k, _ in _Peaks._fields_ if k != "reserved"}
 
 
 class _Params3(ctypes.Structure):
@@ -216,6 +230,8 @@ def load():
     lib.fse_schedule3.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                   ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
     lib.fse_schedule3.restype = ctypes.c_int32
+    lib.fse_measure_peaks.argtypes = [P(_Peaks)]
+    lib.fse_measure_peaks.restype = ctypes.c_int32
     lib.fse_strerror.argtypes = [ctypes.c_int32]
     lib.fse_strerror.restype = ctypes.c_char_p
     _lib = lib

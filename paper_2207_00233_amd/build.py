@@ -15,7 +15,7 @@ LIB = os.path.join(HERE, "libfse.so")
 ARCH = os.environ.get("FSE_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["fse_kernels.hip", "fse_runtime.cpp", "fse_sched.cpp", "fse_serve.cpp",
-           "fse_volume.hip", "fse_volume.cpp"]
+           "fse_volume.hip", "fse_volume.cpp", "fse_peaks.hip"]
 
 # Packed FP32 instructions are switched off for the device code.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

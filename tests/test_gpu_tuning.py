@@ -68,3 +68,16 @@ def test_autotune_sets_the_fastest_tuning():
         assert len(results) == 3
         assert best == min(results, key=lambda r: r[1])[0]
         assert plan.get_tuning() == best
+
+
+def test_measured_peaks_are_plausible():
+    # the microbenchmarks behind the benchmark's measured roofline peaks:
+    # within a factor of the published MI355X figures (FP32 78.6 TFLOP/s
+    # without packed instructions, FP64 78.6, HBM 8 TB/s)
+    pk = fse.measure_peaks()
+    print(f"[gpu] peaks {pk}", flush=True)
+    assert pk["compute_units"] > 0
+    assert 10.0 < pk["fp32_fma_tflops"] < 100.0
+    assert 10.0 < pk["fp64_fma_tflops"] < 100.0
+    assert 5.0 < pk["lds_read_tbps"] < 200.0
+    assert 1.0 < pk["hbm_copy_tbps"] < 10.0
