@@ -137,3 +137,12 @@ def test_volume_full_size_sampled_blocks_teacher_forced():
 def test_volume_parameter_edges(kw):
     v = synth.video_volume(seed=4, frames=7, height=40, width=56, block=8, p=0.25)
     _check(fse.Params3(**kw), v.volume, v.lost)
+
+
+def test_volume_without_losses_is_returned_unchanged():
+    v = synth.video_volume(seed=5, frames=3, height=33, width=47, p=0.0)
+    with fse.Plan3(fse.Params3(iterations=10)) as plan:
+        r = plan.conceal_volume(v.volume, np.zeros_like(v.lost), want_float=True)
+    assert r.waves == 0 and r.lost_blocks == 0
+    np.testing.assert_array_equal(r.out, v.volume)
+    np.testing.assert_array_equal(r.out_f, v.volume.astype(np.float64))
