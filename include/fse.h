@@ -164,11 +164,11 @@ typedef struct {
  * tolerance in every shape, not bit for bit across shapes.
  * FSE_FRAME_GROUPS=g (1..16) sets the number of frame groups of a batched
  * call (default 3 in FSE_FP32_RERANK, 4 when the process runs with
- * GPU_MAX_HW_QUEUES >= 8, else 2).  FSE_CRIT_DEPTH=c (0..1):
+ * GPU_MAX_HW_QUEUES >= 8; 3 in FSE_FP64; else 2).  FSE_CRIT_DEPTH=c (0..1):
  * frames whose schedule has at least c times the waves of the deepest frame
  * form a group of their own, whose workgroups raise their wave priority
  * (FSE_CRIT_PRIO=0 keeps the default priority); 0 = off, default 0.9 in
- * FSE_FP32_RERANK, else off.  FSE_CRIT_WAVES=w (4, 8 or 16;
+ * FSE_FP32_RERANK and FSE_FP64, else off.  FSE_CRIT_WAVES=w (4, 8 or 16;
  * 0 = by that group's launch size) sets the wavefronts per block of that
  * group (default 4 in FSE_FP32_RERANK).  None of these changes results
  * beyond the per-shape rounding noted above.
@@ -341,15 +341,16 @@ int32_t fse_last_call_stats(fse_plan_t plan, fse_call_stats *out);
  *                      (default 0: never); all others on 4;
  *   frame_groups       frame groups of a batched call, 1..16; 0 = by
  *                      precision (3 in FSE_FP32_RERANK, 4 with
- *                      GPU_MAX_HW_QUEUES >= 8, else 2);
+ *                      GPU_MAX_HW_QUEUES >= 8; 3 in FSE_FP64; else 2);
  *   crit_depth         frames with at least this fraction of the deepest
  *                      frame's waves form group 0 (0 = off, at most 1); < 0 =
- *                      by precision (0.9 in FSE_FP32_RERANK, else off);
+ *                      by precision (0.9 in FSE_FP32_RERANK and FSE_FP64,
+ *                      else off);
  *   crit_prio          1: group 0's workgroups raise their wave priority;
  *   crit_waves         wavefronts per block of group 0's launches: 4, 8 or
  *                      16; 0 = by the thresholds above on group 0's own
  *                      launch size; < 0 = by precision (4 in
- *                      FSE_FP32_RERANK).
+ *                      FSE_FP32_RERANK and FSE_FP64).
  * FSE_FP32_F16X3 runs every launch on 4 wavefronts whatever the thresholds.
  * fse_plan_get_tuning reports the values in effect (defaults resolved);
  * fse_plan_set_tuning takes effect for launches issued after it returns

@@ -113,8 +113,10 @@ struct fse_plan_s {
     const int g = groups.load(std::memory_order_relaxed);
     if (g > 0) return g;
     // re-rank: 3 groups fit the default 4 hardware queues (one holds the
-    // caller's stream); with 8 queues a fourth group overlaps as well
-    return p.precision == FSE_FP32_RERANK ? (hw_queues >= 8 ? 4 : 3) : 2;
+    // caller's stream); with 8 queues a fourth group overlaps as well.  FP64
+    // (two blocks per CU): 3 groups
+    if (p.precision == FSE_FP32_RERANK) return hw_queues >= 8 ? 4 : 3;
+    return p.precision == FSE_FP64 ? 3 : 2;
   }
   // frames whose schedule has at least crit_depth() x the waves of the
   // deepest frame of a batch form group 0 (when there are other frames): their
@@ -123,11 +125,13 @@ struct fse_plan_s {
   // and their workgroups raise their wave priority (crit_prio).  0 = off;
   // < 0 = by precision, measured on
   // MI355X with the 64-frame batch: 0.9 for the re-rank mode, whose per-step
-  // transform pass lengthens the chain, else off
+  // transform pass lengthens the chain, and for FP64 (two blocks per CU),
+  // else off
   std::atomic<double> crit{-1.0};
   double crit_depth() const {
     const double c = crit.load(std::memory_order_relaxed);
-    return c >= 0.0 ? c : (p.precision == FSE_FP32_RERANK ? 0.9 : 0.0);
+    return c >= 0.0 ? c
+                    : (p.precision == FSE_FP32_RERANK || p.precision == FSE_FP64 ? 0.9 : 0.0);
   }
   std::atomic<bool> crit_prio{true};
   // wavefronts per block of group 0's launches: 4/8/16; 0 = waves_for() of
@@ -138,7 +142,7 @@ struct fse_plan_s {
   std::atomic<int> crit_waves{-1};
   int crit_waves_for(int64_t n_items) const {
     int c = crit_waves.load(std::memory_order_relaxed);
-    if (c < 0) c = p.precision == FSE_FP32_RERANK ? 4 : 0;
+    if (c < 0) c = p.precision == FSE_FP32_RERANK || p.precision == FSE_FP64 ? 4 : 0;
     return c > 0 ? c : waves_for(n_items);
   }
   std::vector<hipStream_t> gstreams;

@@ -1058,7 +1058,9 @@ int32_t fse_plan_get_tuning(fse_plan_t pl, fse_tuning* out) {
   out->crit_prio = pl->crit_prio.load() ? 1 : 0;
   {
     const int c = pl->crit_waves.load();
-    out->crit_waves = c >= 0 ? c : (pl->p.precision == FSE_FP32_RERANK ? 4 : 0);
+    out->crit_waves =
+        c >= 0 ? c
+               : (pl->p.precision == FSE_FP32_RERANK || pl->p.precision == FSE_FP64 ? 4 : 0);
   }
   return FSE_OK;
 }

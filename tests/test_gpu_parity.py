@@ -290,7 +290,12 @@ def test_single_iteration_and_rho_one():
         check_free_running(p, fr.image, fr.lost, FP64_TOL)
 
 
-def test_batch_equals_single_frames():
+def test_batch_equals_single_frames(monkeypatch):
+    # bit for bit with the workgroup shape pinned (every launch on 4
+    # wavefronts): across shapes results agree only to the stated tolerance,
+    # and a batch may give its deepest frames a shape of their own
+    monkeypatch.setenv("FSE_WAVE_THRESHOLDS", "0,0")
+    monkeypatch.setenv("FSE_CRIT_WAVES", "4")
     rng = np.random.default_rng(8)
     frames = []
     for (H, W) in [(64, 80), (45, 33), (96, 64)]:

@@ -39,6 +39,9 @@ def test_defaults_and_range_checks():
     with fse.Plan(fse.Params(precision=fse.FSE_FP32)) as plan:
         t = plan.get_tuning()
         assert (t["frame_groups"], t["crit_depth"], t["crit_waves"]) == (2, 0.0, 0)
+    with fse.Plan(fse.Params(precision=fse.FSE_FP64)) as plan:
+        t = plan.get_tuning()
+        assert (t["frame_groups"], t["crit_depth"], t["crit_waves"]) == (3, 0.9, 4)
 
 
 @pytest.mark.parametrize("precision", [fse.FSE_FP32_RERANK, fse.FSE_FP32])
