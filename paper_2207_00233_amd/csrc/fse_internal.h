@@ -94,8 +94,9 @@ struct fse_plan_s {
   // at most mid_threshold -> 8, else 4 (fewer blocks than the GPU holds leave
   // SIMDs idle; more wavefronts per block shorten each block's iteration)
   // (the tuning fields are atomic: fse_plan_set_tuning may change them while
-  // the serving worker issues launches)
-  std::atomic<int> wide_threshold{256};
+  // the serving worker issues launches).  128: the autotuner's best on the
+  // 64-frame batch in the re-rank and FP32 modes (1-2 % ahead of 256)
+  std::atomic<int> wide_threshold{128};
   std::atomic<int> mid_threshold{0};
   int waves_for(int64_t n_items) const {
     return n_items <= wide_threshold.load(std::memory_order_relaxed)

@@ -27,7 +27,7 @@ def test_defaults_and_range_checks():
         t = plan.get_tuning()
         groups = 4 if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) >= 8 else 3
         assert (t["wave_threshold_16"], t["wave_threshold_8"], t["frame_groups"],
-                t["crit_depth"], t["crit_prio"], t["crit_waves"]) == (256, 0, groups, 0.9, 1, 4)
+                t["crit_depth"], t["crit_prio"], t["crit_waves"]) == (128, 0, groups, 0.9, 1, 4)
         for bad in ({"frame_groups": 17}, {"frame_groups": -1}, {"crit_depth": 1.5},
                     {"wave_threshold_16": -1}, {"crit_prio": 2}, {"crit_waves": 2},
                     {"crit_waves": 32}):
