@@ -146,3 +146,15 @@ def test_volume_without_losses_is_returned_unchanged():
     assert r.waves == 0 and r.lost_blocks == 0
     np.testing.assert_array_equal(r.out, v.volume)
     np.testing.assert_array_equal(r.out_f, v.volume.astype(np.float64))
+
+
+def test_volume_largest_iteration_count():
+    # K = FSE_MAX_ITERATIONS: the selection history fills the LDS to its
+    # largest size (153 KB); tiny 3 x 4 x 4 areas keep the oracle quick
+    rng = np.random.default_rng(9)
+    vol = rng.integers(0, 256, (3, 8, 8)).astype(np.uint8)
+    lost = np.zeros_like(vol)
+    lost[1, 2:4, 4:6] = 1
+    lost[2, 6:8, 0:2] = 1
+    p = fse.Params3(block_t=1, block_h=2, block_w=2, border_t=1, border_d=1, iterations=1024)
+    _check(p, vol, lost)
