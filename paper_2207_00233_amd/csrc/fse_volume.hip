@@ -249,9 +249,14 @@ __global__ __launch_bounds__(kVThreads, 1) void fse_volume_block_kernel(Vol3Args
         ri[j] = y;
         e[j] = fma(x, x, y * y);
       }
-      double be = e[0];
+      double t8[kVEnt / 2];  // the thread's largest |R|^2 as a tree of maxima
 #pragma unroll
-      for (int j = 1; j < kVEnt; ++j) be = fmax(be, e[j]);
+      for (int j = 0; j < kVEnt / 2; ++j) t8[j] = fmax(e[2 * j], e[2 * j + 1]);
+#pragma unroll
+      for (int w = kVEnt / 4; w >= 1; w >>= 1)
+#pragma unroll
+        for (int j = 0; j < w; ++j) t8[j] = fmax(t8[2 * j], t8[2 * j + 1]);
+      const double be = t8[0];
       // wavefront: the largest |R|^2; the entry holding it is the lowest
       // entry index j, then the lowest lane, among those equal to it (for
       // equal values the smallest index (k1 32 + k2) 32 + k3 = kbase + 512 j)
