@@ -277,3 +277,24 @@ def test_schedule_properties_recounted_from_the_definition():
             for b in members:
                 pending[b] = False
         assert not pending.any()
+
+
+def test_isolated_losses_give_the_same_volume_in_both_orders():
+    # 3-D analogue of the paper's isolated-loss rows (0.00 dB between the
+    # orders): lost blocks with no lost 26-neighbour and areas that reach no
+    # further than the neighbouring blocks (d_t <= B_t, d <= B) read only
+    # known samples, so the processing order cannot matter: bit for bit equal
+    rng = np.random.default_rng(21)
+    T, H, W = 6, 48, 64
+    vol = rng.integers(0, 256, (T, H, W)).astype(np.uint8)
+    lost = np.zeros_like(vol)
+    for t in range(0, T, 2):
+        for i in range(0, H // 8, 2):
+            for j in range(0, W // 8, 2):
+                if rng.random() < 0.6:
+                    lost[t, 8 * i:8 * i + 8, 8 * j:8 * j + 8] = 1
+    kw = dict(block_t=1, block_h=8, block_w=8, border_t=1, border_d=8, iterations=20)
+    a = oracle.conceal3(oracle.Params3(order=oracle.ORDER_OPTIMIZED, **kw), vol, lost)
+    b = oracle.conceal3(oracle.Params3(order=oracle.ORDER_LINESCAN, **kw), vol, lost)
+    assert a.waves < b.waves == int(lost[:, ::8, ::8].sum())
+    np.testing.assert_array_equal(a.volume, b.volume)
