@@ -186,3 +186,35 @@ def test_refined_grid_offsets_and_ragged_edges(shape, off):
         torch.cuda.synchronize()
     np.testing.assert_array_equal(to.cpu().numpy(), r.out)
     np.testing.assert_array_equal(tf.cpu().numpy(), r.out_f)
+
+
+@pytest.mark.parametrize("precision,tol", [(fse.FSE_FP64, FP64_TOL * 255),
+                                           (fse.FSE_FP32_RERANK, FP32_TOL)])
+def test_refined_full_size_holes_sampled_blocks(precision, tol):
+    """The refined-order experiment's own input at its full size: a 512 x 512
+    polygon image with 300 unaligned holes of 1..12 x 1..12 samples plus
+    isolated 16 x 16 losses (p = 0.12), d = 16, K = 200.  The GPU runs the
+    whole frame; blocks sampled from the first, middle and last waves are
+    teacher-forced against the oracle (the area each one read is rebuilt
+    from the GPU's final image and the oracle's schedule)."""
+    rng = np.random.default_rng(0)
+    img = synth.polygon_image(rng, 512, 512)
+    lost = np.maximum(synth.hole_loss(rng, 512, 512, 300),
+                      synth.isolated_block_loss(rng, 512, 512, 16, 0.12))
+    p = fse.Params(border_d=16, iterations=200, precision=precision, order=fse.FSE_ORDER_REFINED)
+    print(f"[gpu] refined order 512x512 holes prec={precision}", flush=True)
+    with fse.Plan(p) as plan:
+        r = plan.fse_conceal_image([img], [lost], want_float=True)[0]
+    op = _oracle_params(p)
+    _, wave_of, seq = oracle.schedule_refined(_block_counts(lost), 256)
+    assert r.waves == int(wave_of.max()) + 1
+    wb = wave_of.shape[1]
+    picks = list(seq[:4]) + list(np.random.default_rng(1).choice(seq, 6, replace=False)) + list(seq[-4:])
+    worst = 0.0
+    for b in picks:
+        o_v, g_v, _ = teacher_forced_block(img, lost, r.out_f.astype(np.float64), wave_of, op,
+                                           b // wb, b % wb)
+        worst = max(worst, float(np.abs(o_v - g_v).max()))
+    print(f"[parity] refined 512x512 prec={precision}: worst {worst:.3e} over {len(picks)} blocks",
+          flush=True)
+    assert worst <= tol
