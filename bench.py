@@ -53,6 +53,7 @@ CLOCK_HZ = 2.4e9
 # sources whose change invalidates a committed traffic measurement: the
 # kernels and the host code that chooses their launches
 TRAFFIC_SOURCES = ("paper_2207_00233_amd/csrc/fse_kernels.hip", "paper_2207_00233_amd/csrc/fse_device.h",
+                   "paper_2207_00233_amd/csrc/fse_dft.h",
                    "paper_2207_00233_amd/csrc/fse_runtime.cpp", "paper_2207_00233_amd/csrc/fse_internal.h")
 
 

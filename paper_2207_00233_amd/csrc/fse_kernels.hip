@@ -30,6 +30,7 @@
 #include <type_traits>
 
 #include "fse_device.h"
+#include "fse_dft.h"
 
 namespace fse {
 
@@ -803,52 +804,8 @@ constexpr int kDp = 72;  // row pitch of the FP64 transform grid (complex)
 
 __device__ __forceinline__ int dpos(int p) { return p + (p >> 3); }
 
-// v * e^{-j theta} with t = (cos theta, sin theta)
-__device__ __forceinline__ double2 dmul_conj(double2 v, double2 t) {
-  return make_double2(fma(v.x, t.x, v.y * t.y), fma(v.y, t.x, -v.x * t.y));
-}
-
-__device__ __forceinline__ double2 dadd(double2 a, double2 b) {
-  return make_double2(a.x + b.x, a.y + b.y);
-}
-__device__ __forceinline__ double2 dsub(double2 a, double2 b) {
-  return make_double2(a.x - b.x, a.y - b.y);
-}
-
-// out[k] = sum_n v[n] e^{-j 2 pi n k / 8}, in place: two 4-point DFTs of the
-// even and odd samples, joined with the factors e^{-j 2 pi k / 8}
-__device__ __forceinline__ void dft8(double2 (&v)[8]) {
-  constexpr double c = 0.70710678118654752440;  // 1 / sqrt(2)
-  double2 e[4], o[4];
-  {
-    const double2 t0 = dadd(v[0], v[4]), t1 = dsub(v[0], v[4]);
-    const double2 t2 = dadd(v[2], v[6]), t3 = dsub(v[2], v[6]);
-    e[0] = dadd(t0, t2);
-    e[2] = dsub(t0, t2);
-    e[1] = make_double2(t1.x + t3.y, t1.y - t3.x);  // t1 - j t3
-    e[3] = make_double2(t1.x - t3.y, t1.y + t3.x);  // t1 + j t3
-  }
-  {
-    const double2 t0 = dadd(v[1], v[5]), t1 = dsub(v[1], v[5]);
-    const double2 t2 = dadd(v[3], v[7]), t3 = dsub(v[3], v[7]);
-    o[0] = dadd(t0, t2);
-    o[2] = dsub(t0, t2);
-    o[1] = make_double2(t1.x + t3.y, t1.y - t3.x);
-    o[3] = make_double2(t1.x - t3.y, t1.y + t3.x);
-  }
-  // o[k] e^{-j 2 pi k / 8}: k = 1: c (1 - j), k = 2: -j, k = 3: -c (1 + j)
-  const double2 p1 = make_double2(c * (o[1].x + o[1].y), c * (o[1].y - o[1].x));
-  const double2 p2 = make_double2(o[2].y, -o[2].x);
-  const double2 p3 = make_double2(c * (o[3].y - o[3].x), -c * (o[3].x + o[3].y));
-  v[0] = dadd(e[0], o[0]);
-  v[4] = dsub(e[0], o[0]);
-  v[1] = dadd(e[1], p1);
-  v[5] = dsub(e[1], p1);
-  v[2] = dadd(e[2], p2);
-  v[6] = dsub(e[2], p2);
-  v[3] = dadd(e[3], p3);
-  v[7] = dsub(e[3], p3);
-}
+using dft::dft8;
+__device__ __forceinline__ double2 dmul_conj(double2 v, double2 t) { return dft::cmul_conj(v, t); }
 
 }  // namespace
 
