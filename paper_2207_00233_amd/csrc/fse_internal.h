@@ -86,6 +86,7 @@ struct fse_plan_s {
   // pinned staging of the lost-block flags (device frames) and of the work
   // items of a call; ev_flags / ev_items mark their copies done
   fse::HostBuf pin_flags, pin_items;
+  fse::HostBuf pin_cnt;  // pinned copy of the re-scoring statistics
   hipEvent_t ev_flags = nullptr, ev_items = nullptr;
   bool items_recorded = false;
   fse::HostPool* pool = nullptr;  // host workers (scheduling, host frame copies)

@@ -474,9 +474,15 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n, bool noallo
 
   // processing order per frame
   std::vector<std::vector<int32_t>> wave_of(n), seq(n);
-  // frames are scheduled independently, on the plan's host workers
+  // frames are scheduled independently, on the plan's host workers, the
+  // largest grids first (the last frame taken should be a small one)
   std::vector<int> nwaves(n, 0);
-  parallel_for(pl, n, [&](int f) {
+  std::vector<int> by_size(n);
+  for (int f = 0; f < n; ++f) by_size[f] = f;
+  std::stable_sort(by_size.begin(), by_size.end(),
+                   [&](int x, int y) { return (int64_t)hb[x] * wb[x] > (int64_t)hb[y] * wb[y]; });
+  parallel_for(pl, n, [&](int i) {
+    const int f = by_size[i];
     wave_of[f].resize((size_t)hb[f] * wb[f]);
     nwaves[f] = refined ? schedule_blocks_refined(hb[f], wb[f], count_base + io[f].flag_off,
                                                   Bh * Bw, wave_of[f].data(), &seq[f])
@@ -541,13 +547,15 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n, bool noallo
     for (auto& v : gframes) std::sort(v.begin(), v.end());
   }
   const bool fp64 = p.precision == FSE_FP64;
-  std::vector<int32_t> items;
-  std::vector<std::pair<int, int32_t>> item_src;  // (frame, block) per item
   // gstart[g][t] = first item of step t of group g (items of all groups in
-  // one array, group after group)
+  // one array, group after group); each group's items are laid out on a host
+  // worker of their own, then joined
   std::vector<std::vector<int64_t>> gstart(G);
-  int max_steps = 0;
-  for (int g = 0; g < G; ++g) {
+  std::vector<std::vector<int32_t>> gitems(G);
+  std::vector<std::vector<std::pair<int, int32_t>>> gsrc(G);
+  parallel_for(pl, G, [&](int g) {
+    std::vector<int32_t>& items = gitems[g];
+    std::vector<std::pair<int, int32_t>>& item_src = gsrc[g];
     const std::vector<int>& fs = gframes[g];
     const int m = (int)fs.size();
     std::vector<int> off(m, 0);
@@ -581,7 +589,22 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n, bool noallo
       }
     }
     gstart[g][steps] = (int64_t)items.size() / 2;
-    max_steps = std::max(max_steps, steps);
+  });
+  std::vector<int32_t> items;
+  std::vector<std::pair<int, int32_t>> item_src;  // (frame, block) per item
+  int max_steps = 0;
+  {
+    size_t ni = 0;
+    for (int g = 0; g < G; ++g) ni += gsrc[g].size();
+    items.reserve(2 * ni);
+    item_src.reserve(ni);
+    for (int g = 0; g < G; ++g) {
+      const int64_t base = (int64_t)item_src.size();
+      for (int64_t& x : gstart[g]) x += base;
+      items.insert(items.end(), gitems[g].begin(), gitems[g].end());
+      item_src.insert(item_src.end(), gsrc[g].begin(), gsrc[g].end());
+      max_steps = std::max(max_steps, (int)gstart[g].size() - 1);
+    }
   }
   const int64_t n_items = (int64_t)items.size() / 2;
 
@@ -658,6 +681,7 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n, bool noallo
   // re-scoring statistics of this call
   if (rerank) {
     if ((rc = pl->counters.reserve(kCntSlots * sizeof(unsigned long long))) ||
+        (!noalloc && (rc = pl->pin_cnt.reserve(kCntSlots * sizeof(unsigned long long)))) ||
         (rc = chk(hipMemsetAsync(pl->counters.ptr, 0, kCntSlots * sizeof(unsigned long long), s))))
       return rc;
     a.counters = (unsigned long long*)pl->counters.ptr;
@@ -669,7 +693,11 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n, bool noallo
   int n_launch = 0;
   for (int g = 0; g < G; ++g)
     for (size_t t = 0; t + 1 < gstart[g].size(); ++t) n_launch += gstart[g][t + 1] > gstart[g][t];
-  // timing events around every launch (not in the noalloc form)
+  // timing events (not in the noalloc form): per launch a marker before the
+  // transform pass, one before and one after the iteration kernel; a group's
+  // consecutive launches share the marker between them (every recorded event
+  // is a packet its queue processes between two kernels: three per launch
+  // cost 2-5 % of a batch).  Two more bracket the call's launches.
   const bool timed = !noalloc;
   while (timed && (int)pl->events.size() < 3 * n_launch + 2) {
     hipEvent_t e;
@@ -681,6 +709,16 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n, bool noallo
   if (timed && (rc = chk(hipEventRecord(ev_fork, s)))) return rc;  // G > 1 implies timed
   for (int g = 1; g < G; ++g)
     if ((rc = chk(hipStreamWaitEvent(pl->gstreams[g - 1], ev_fork, 0)))) return rc;
+  struct LaunchMarks {
+    int pre, mid, post;  // indices into pl->events
+  };
+  std::vector<LaunchMarks> marks(timed ? n_launch : 0);
+  std::vector<int> tail(G, -1);  // marker at the tail of a group's stream, -1 = none
+  int n_ev = 0;
+  auto mark = [&](hipStream_t st, int& idx) {
+    idx = n_ev++;
+    return chk(hipEventRecord(pl->events[idx], st));
+  };
   int li = 0;
   for (int t = 0; t < max_steps; ++t) {
     // blocks of this step over all groups, for the workgroup shape
@@ -699,16 +737,31 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n, bool noallo
       if (rerank) a.spec64 = (double*)pl->spec64.ptr + spec_base[g] * kSpecStride;
       const int waves =
           mx ? 4 : (crit_group && g == 0 ? pl->crit_waves_for(cnt) : pl->waves_for(step_total));
-      if (timed && (rc = chk(hipEventRecord(pl->events[3 * li], gs)))) return rc;
+      LaunchMarks m{-1, -1, -1};
+      if (timed) {
+        if (tail[g] >= 0)
+          m.pre = tail[g];
+        else if ((rc = mark(gs, m.pre)))
+          return rc;
+      }
       if constexpr (std::is_same<T, float>::value) {
         if (rerank &&
             (rc = chk(launch_dft64(a, (const double*)pl->tbl_radial64.ptr, (int)cnt, gs))))
           return rc;
       }
-      if (timed && (rc = chk(hipEventRecord(pl->events[3 * li + 1], gs)))) return rc;
+      if (timed) {
+        if (!rerank)
+          m.mid = m.pre;
+        else if ((rc = mark(gs, m.mid)))
+          return rc;
+      }
       if ((rc = chk(launch_block<T>(a, (int)cnt, waves, gs, rerank ? 1 : (mx ? 2 : 0)))))
         return rc;
-      if (timed && (rc = chk(hipEventRecord(pl->events[3 * li + 2], gs)))) return rc;
+      if (timed) {
+        if ((rc = mark(gs, m.post))) return rc;
+        marks[li] = m;
+        tail[g] = staged ? -1 : m.post;  // the scatter kernel follows in the staged form
+      }
       if (staged && (rc = chk(launch_scatter<T>(work, state, a.frames, a.items, (int)cnt,
                                                 (const T*)pl->staging.ptr, Bh, Bw, gox, goy, gs))))
         return rc;
@@ -724,6 +777,12 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n, bool noallo
 
   // outputs
   if ((rc = chk(launch_finalize<T>((const IoDesc*)pl->io_dev.ptr, n, max_pixels, state, work, s))))
+    return rc;
+  // the re-scoring statistics come back with the outputs (through pinned
+  // staging; the noalloc form copies them after the wait)
+  if (a.counters && !noalloc &&
+      (rc = chk(hipMemcpyAsync(pl->pin_cnt.ptr, a.counters, kCntSlots * sizeof(unsigned long long),
+                               hipMemcpyDeviceToHost, s))))
     return rc;
   if (!dev) {
     if ((rc = chk(hipMemcpyAsync(pl->pin_out.ptr, pl->u8_out.ptr, total, hipMemcpyDeviceToHost, s))))
@@ -750,12 +809,16 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n, bool noallo
     });
   }
 
+  // device time of every marker from the fork (one query per marker)
+  std::vector<float> at(timed ? n_ev : 0, 0.f);
+  std::vector<char> at_ok(at.size(), 0);
+  for (size_t i = 0; i < at.size(); ++i)
+    at_ok[i] = hipEventElapsedTime(&at[i], ev_fork, pl->events[i]) == hipSuccess;
   double kms = 0.0, tms = 0.0;
   for (int t = 0; timed && t < n_launch; ++t) {
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, pl->events[3 * t + 1], pl->events[3 * t + 2]) == hipSuccess) kms += ms;
-    if (rerank && hipEventElapsedTime(&ms, pl->events[3 * t], pl->events[3 * t + 1]) == hipSuccess)
-      tms += ms;
+    const LaunchMarks& m = marks[t];
+    if (at_ok[m.mid] && at_ok[m.post]) kms += at[m.post] - at[m.mid];
+    if (rerank && at_ok[m.pre] && at_ok[m.mid]) tms += at[m.mid] - at[m.pre];
   }
   float span = 0.f;
   if (timed) (void)hipEventElapsedTime(&span, ev_fork, ev_end);
@@ -765,12 +828,8 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n, bool noallo
   if (timed) {
     std::vector<std::pair<float, float>> iv;
     iv.reserve(n_launch);
-    for (int t = 0; t < n_launch; ++t) {
-      float a0 = 0.f, a1 = 0.f;
-      if (hipEventElapsedTime(&a0, ev_fork, pl->events[3 * t + 1]) == hipSuccess &&
-          hipEventElapsedTime(&a1, ev_fork, pl->events[3 * t + 2]) == hipSuccess)
-        iv.emplace_back(a0, a1);
-    }
+    for (int t = 0; t < n_launch; ++t)
+      if (at_ok[marks[t].mid] && at_ok[marks[t].post]) iv.emplace_back(at[marks[t].mid], at[marks[t].post]);
     std::sort(iv.begin(), iv.end());
     float lo = 0.f, hi = -1.f;
     for (const auto& x : iv) {
@@ -788,7 +847,10 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n, bool noallo
       pl->last.rescore_max_wave = 0;
   if (a.counters) {
     unsigned long long cnt[kCntSlots];
-    if ((rc = chk(hipMemcpy(cnt, a.counters, sizeof(cnt), hipMemcpyDeviceToHost)))) return rc;
+    if (!noalloc)
+      std::memcpy(cnt, pl->pin_cnt.ptr, sizeof(cnt));
+    else if ((rc = chk(hipMemcpy(cnt, a.counters, sizeof(cnt), hipMemcpyDeviceToHost))))
+      return rc;
     pl->last.rescored = (int64_t)cnt[kCntRescored];
     pl->last.rescore_candidates = (int64_t)cnt[kCntCandidates];
     pl->last.rescore_wide = (int64_t)cnt[kCntWide];
@@ -965,6 +1027,7 @@ int32_t fse_plan_destroy(fse_plan_t pl) {
   pl->pin_out.release();
   pl->pin_flags.release();
   pl->pin_items.release();
+  pl->pin_cnt.release();
   if (pl->ev_flags) (void)hipEventDestroy(pl->ev_flags);
   if (pl->ev_items) (void)hipEventDestroy(pl->ev_items);
   delete pl->pool;
