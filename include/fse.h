@@ -213,7 +213,7 @@ int32_t fse_conceal_image(fse_plan_t plan, const fse_frame *frames, int32_t n);
  * bit.  Errors: FSE_ERR_INVALID (as fse_conceal_image, a plan without
  * FSE_FLAG_DEVICE_PTRS, a frame with a trace), FSE_ERR_NOMEM (the call needs
  * more than FSE_NOALLOC_SCRATCH_BYTES of scratch: roughly 5 bytes per pixel
- * in FSE_FP32, 9 in FSE_FP64, plus 131 KB per block of the largest wave in
+ * in FSE_FP32, 9 in FSE_FP64, plus 66 KB per block of the largest wave in
  * FSE_FP32_RERANK), FSE_ERR_DEVICE.
  */
 #define FSE_NOALLOC_SCRATCH_BYTES ((int64_t)128 << 20)
@@ -301,8 +301,8 @@ int32_t fse_schedule_refined(int32_t hb, int32_t wb, const int32_t *unknown, int
  *                its launches (HIP events around every launch);
  *   launches     number of those launches;  blocks: blocks they processed;
  *   total_ms     host wall time of the call;
- *   transform_ms device time of the FP64 transform pass, summed over its
- *                launches (FSE_FP32_RERANK only);
+ *   transform_ms 0 (the transforms run inside the per-block kernel in every
+ *                mode; the field is kept for the layout);
  *   span_ms      device time from the first to the end of the last
  *                extrapolation launch (all groups);
  *   groups       number of frame groups;
@@ -339,18 +339,15 @@ int32_t fse_last_call_stats(fse_plan_t plan, fse_call_stats *out);
  *                      wavefronts per block (default 128);
  *   wave_threshold_8   larger launches of at most this many blocks run on 8
  *                      (default 0: never); all others on 4;
- *   frame_groups       frame groups of a batched call, 1..16; 0 = by
- *                      precision (3 in FSE_FP32_RERANK, 4 with
- *                      GPU_MAX_HW_QUEUES >= 8; 3 in FSE_FP64; else 2);
+ *   frame_groups       frame groups of a batched call, 1..16; 0 = the
+ *                      default, 3;
  *   crit_depth         frames with at least this fraction of the deepest
  *                      frame's waves form group 0 (0 = off, at most 1); < 0 =
- *                      by precision (0.9 in FSE_FP32_RERANK and FSE_FP64,
- *                      else off);
+ *                      the default, 0.9;
  *   crit_prio          1: group 0's workgroups raise their wave priority;
  *   crit_waves         wavefronts per block of group 0's launches: 4, 8 or
  *                      16; 0 = by the thresholds above on group 0's own
- *                      launch size; < 0 = by precision (4 in
- *                      FSE_FP32_RERANK and FSE_FP64).
+ *                      launch size; < 0 = the default, 4.
  * FSE_FP32_F16X3 runs every launch on 4 wavefronts whatever the thresholds.
  * fse_plan_get_tuning reports the values in effect (defaults resolved);
  * fse_plan_set_tuning takes effect for launches issued after it returns

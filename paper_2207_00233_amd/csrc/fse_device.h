@@ -37,6 +37,7 @@ struct BlockArgs {
   const FrameDesc* frames;
   const int32_t* items;    // 2 ints per work item: frame | priority << 24, (bi << 16) | bj
   const T* radial;         // M*N table rho^dist of Eq. (2)
+  const double* radial64;  // the same table in double (re-rank transforms)
   const T* twid;           // 64 x (cos, sin)(2 pi t / 64) in T
   const double* twid64;    // 64 x (cos, sin)(2 pi t / 64) in double
   T* staging;              // nullable: results go here (d > block size)
@@ -66,12 +67,14 @@ enum : int {
 constexpr int32_t kItemFrameMask = 0xffffff;
 constexpr int kItemPrioShift = 24;
 
-// FP64 spectra of one work item written by the FP64 transform pass of the
-// re-rank mode: R0 (64 x 64 complex), W (64 x 64 complex), then W0.
+// FP64 spectra of one work item written by the re-rank mode's transforms:
+// R0, then W, each the columns k2 = 0..32 of its 64 rows (complex, row
+// pitch 33; the spectra of real data are Hermitian, the other columns are
+// the conjugates of these).
 constexpr int64_t kSpecR0 = 0;                      // in doubles
-constexpr int64_t kSpecW = 2 * kFft * kFft;
-constexpr int64_t kSpecW0 = 4 * kFft * kFft;
-constexpr int64_t kSpecStride = 4 * kFft * kFft + 32;  // doubles per item (256-byte aligned)
+constexpr int64_t kSpecW = 2 * kFft * kHalf;
+constexpr int64_t kSpecStride = 4 * kFft * kHalf;   // doubles per item (256-byte multiple)
+static_assert(kSpecStride * 8 % 256 == 0, "items' spectra stay 256-byte aligned");
 
 // Byte offsets of the dynamic LDS regions of the fused block kernel with
 // `waves` wavefronts per workgroup (rows = 64 / waves spectrum rows each).
@@ -115,7 +118,11 @@ __host__ __device__ inline LdsLayout lds_layout(int M, int N, int K, int waves, 
   // wavefronts (split rows), of `rows` rows otherwise
   const int wrap = waves == 4 ? rows / 2 - 1 : rows - 1;
   const int64_t wreg = (int64_t)(kFft + wrap) * kFft * 2 * tsize;
-  const int64_t region = align16(stage > wreg ? stage : wreg);
+  // the re-rank mode's FP64 transforms use the region first: 64 rows of 33
+  // complex doubles
+  const int64_t fp64_grid = stage_needed ? 0 : (int64_t)kFft * kHalf * 16;
+  const int64_t big = wreg > fp64_grid ? wreg : fp64_grid;
+  const int64_t region = align16(stage > big ? stage : big);
   L.hist_dc = region;
   L.hist_u = L.hist_dc + (int64_t)K * 2 * tsize;
   L.tw64 = align16(L.hist_u + (int64_t)K * 4);
@@ -128,11 +135,6 @@ __host__ __device__ inline LdsLayout lds_layout(int M, int N, int K, int waves, 
   L.total = L.misc + 32;
   return L;
 }
-
-// LDS of the FP64 transform pass of the re-rank mode: the 64 x 64 complex
-// double grid with a pad entry after every 8 (row pitch 72), the 64
-// twiddles, 4 partial sums.
-constexpr int64_t kDftLdsBytes = 64LL * 72 * 16 + 64 * 16 + 32;
 
 template <typename T>
 inline int64_t lds_bytes(int M, int N, int K, int waves, bool stage_needed = true) {

@@ -106,45 +106,36 @@ struct fse_plan_s {
   }
   bool stagger = true;       // staggered frame starts inside a batch
   // frames of a batch run in up to `groups` groups on streams of their own
-  // (0: by precision, measured on MI355X with the 64-frame batch: 3 groups
-  // for the re-rank mode, whose two kernels per step overlap best (4 with 8
-  // hardware queues), else 2; more groups than hardware queues serialize)
+  // (0: the default, 3, measured on MI355X with the 64-frame batch in every
+  // precision; with the critical group below, 3 groups ran 2-8 % ahead of 2
+  // and 4; 3 streams also fit HIP's default 4 hardware queues)
   std::atomic<int> groups{0};
-  int hw_queues = 4;  // hardware queues of the process (GPU_MAX_HW_QUEUES, HIP's default 4)
   int group_count() const {
     const int g = groups.load(std::memory_order_relaxed);
-    if (g > 0) return g;
-    // re-rank: 3 groups fit the default 4 hardware queues (one holds the
-    // caller's stream); with 8 queues a fourth group overlaps as well.  FP64
-    // (two blocks per CU): 3 groups
-    if (p.precision == FSE_FP32_RERANK) return hw_queues >= 8 ? 4 : 3;
-    return p.precision == FSE_FP64 ? 3 : 2;
+    return g > 0 ? g : 3;
   }
   // frames whose schedule has at least crit_depth() x the waves of the
   // deepest frame of a batch form group 0 (when there are other frames): their
   // chain of waves bounds the batch, so they start first, their launches take
   // a wavefront count of their own (crit_waves) instead of the step total's,
   // and their workgroups raise their wave priority (crit_prio).  0 = off;
-  // < 0 = by precision, measured on
-  // MI355X with the 64-frame batch: 0.9 for the re-rank mode, whose per-step
-  // transform pass lengthens the chain, and for FP64 (two blocks per CU),
-  // else off
+  // < 0 = the default, 0.9 (measured on MI355X with the 64-frame batch: 7-20 %
+  // ahead of no critical group in every precision)
   std::atomic<double> crit{-1.0};
   double crit_depth() const {
     const double c = crit.load(std::memory_order_relaxed);
-    return c >= 0.0 ? c
-                    : (p.precision == FSE_FP32_RERANK || p.precision == FSE_FP64 ? 0.9 : 0.0);
+    return c >= 0.0 ? c : 0.9;
   }
   std::atomic<bool> crit_prio{true};
   // wavefronts per block of group 0's launches: 4/8/16; 0 = waves_for() of
-  // the group's own launch size; < 0 = by precision, measured on MI355X with
-  // the 64-frame batch: 4 for the re-rank mode (16 wavefronts shorten a
-  // block's iterations but cost 1.7x its vector instructions, and group 0
-  // shares the GPU with the other groups)
+  // the group's own launch size; < 0 = the default, 4 (measured on MI355X
+  // with the 64-frame batch: 16 wavefronts shorten a block's iterations but
+  // cost 1.7x its vector instructions, and group 0 shares the GPU with the
+  // other groups)
   std::atomic<int> crit_waves{-1};
   int crit_waves_for(int64_t n_items) const {
     int c = crit_waves.load(std::memory_order_relaxed);
-    if (c < 0) c = p.precision == FSE_FP32_RERANK || p.precision == FSE_FP64 ? 4 : 0;
+    if (c < 0) c = 4;
     return c > 0 ? c : waves_for(n_items);
   }
   std::vector<hipStream_t> gstreams;

@@ -780,78 +780,104 @@ __device__ __forceinline__ void load_twiddles(unsigned char* smem, const LdsLayo
   }
 }
 
-// FP64 transform pass of the re-rank mode: writes R0 = DFT(x), W = DFT(w)
-// and W0 of every work item in double to BlockArgs::spec64 (the iteration
-// kernel runs in float).  One workgroup of 4 wavefronts per item; x = f w and
-// then w go through the same steps, each on its own (a packed transform of
-// x + j s w would leak the rounding of one into the other: a black area
-// would not give X = 0 exactly):
-//  A: gather and weight the area (Eq. (2)) onto the 64 x 64 grid in LDS
-//     (zeros outside the area);
-//  B: the 2-D DFT as 64-point transforms along rows, then along columns,
-//     each factorized 8 x 8: an 8-point DFT over n1 of z[8 n1 + n2], the
-//     twiddle e^{-j 2 pi n2 k1 / 64}, an 8-point DFT over n2 (output
-//     k1 + 8 k2).  Every 8-point DFT runs in one thread's registers, in
-//     place: the position 8 a + b of a row holds after the pass the frequency
-//     a + 8 b.  A row of 64 positions is stored as 8 groups of 8 with one pad
-//     entry per group, so that the eight lanes of a group of lanes hit
-//     distinct banks in both access patterns;
-//  C: the spectrum out in coalesced rows of 1 KB.
-// LDS 74 KB: two workgroups per CU.
+// FP64 transforms of the re-rank mode, inside the block kernel: W = DFT(w)
+// and R0 = DFT(x) in double, written to BlockArgs::spec64 for the exact
+// re-scoring and handed to the float iteration (rr/ri in registers, W read
+// back as floats; k1 = row_of(wave, j), k2 = lane).  w and x = f w are real,
+// so their spectra are Hermitian (S[-k] = conj S[k]) and columns k2 = 0..32
+// hold all of it: the grid is 64 rows x 32 complex slots (33 KB, inside the
+// block's own LDS).  w and x go through the same steps one after the other (a
+// packed transform of x + j s w would leak the rounding of one into the
+// other: a black area would not give X = 0 exactly):
+//  A: gather and weight the area (Eq. (2)); row m, slot p holds the sample
+//     pair (z[2p], z[2p+1]) as one complex value (zeros outside the area);
+//  B: per row, the 32-point DFT Z of those pairs, factorized 8 x 4 (an
+//     8-point DFT over n1 of slot 4 n1 + n2, the twiddle e^{-j 2 pi n2 k1 /
+//     32}, a 4-point DFT over n2), then the row's real 64-point DFT from the
+//     pairs (Z[k], Z[32 - k]): with E and O the DFTs of the even and odd
+//     samples, X[k] = E[k] + e^{-j 2 pi k / 64} O[k] and X[32 - k] =
+//     conj(E[k] - e^{-j 2 pi k / 64} O[k]).  One thread takes the 4-point
+//     DFTs k1 and 8 - k1 of a row, which hold every pair it needs, and puts
+//     its eight results back into its own eight slots: slot kHalfSlot[k]
+//     holds X[k], the two real values X[0] and X[32] share one slot;
+//  C: per slot, the 64-point DFT along the rows, factorized 8 x 8 as in B
+//     (output row 8 (K & 7) + (K >> 3) holds frequency K); the shared slot
+//     transforms X[.][0] + j X[.][32], whose two columns are separated on the
+//     way out;
+//  D: out: row K of the spectrum, columns 0..32, to HBM (and for x the
+//     lane's entries, columns above 32 from the conjugate entry, to
+//     registers).
+// Returns W0 (0 when the area has no support: nothing is written then).
+constexpr int kHp = 33;  // grid pitch in complex doubles (one pad slot)
+static_assert(kFft * kHp * 16 <= (kFft + 3) * kFft * 8,
+              "the half-spectrum grid fits in the block kernel's W region");
+
+// slot of column k2 = 0..32 after the row transforms (0 and 32 share one)
+__constant__ unsigned char kHalfSlot[kHalf] = {18, 4,  8,  12, 2,  22, 26, 30, 0,  6,  10,
+                                               14, 16, 20, 24, 28, 19, 29, 25, 21, 17, 15,
+                                               11, 7,  1,  31, 27, 23, 3,  13, 9,  5,  18};
+
+// entry (k1, k2) of the spectrum of real data stored as columns 0..32
+__device__ __forceinline__ double2 half_spec_at(const double* s, int k1, int k2) {
+  const bool hi = k2 > kFft / 2;
+  const int r = hi ? (kFft - k1) & (kFft - 1) : k1, c = hi ? kFft - k2 : k2;
+  const double2 v = *reinterpret_cast<const double2*>(s + 2 * (r * kHalf + c));
+  return make_double2(v.x, hi ? -v.y : v.y);
+}
+
 namespace {
 
-constexpr int kDp = 72;  // row pitch of the FP64 transform grid (complex)
-
-__device__ __forceinline__ int dpos(int p) { return p + (p >> 3); }
-
+using dft::dft4;
 using dft::dft8;
 __device__ __forceinline__ double2 dmul_conj(double2 v, double2 t) { return dft::cmul_conj(v, t); }
+__device__ __forceinline__ double2 dconj(double2 v) { return make_double2(v.x, -v.y); }
+
+// X[k] and X[32 - k] of a real row from Z[k] and Z[32 - k] (t = the twiddle
+// of k as (cos, sin))
+__device__ __forceinline__ void real_pair(double2 zk, double2 zp, double2 t, double2& xk,
+                                          double2& xp) {
+  const double2 e = make_double2(0.5 * (zk.x + zp.x), 0.5 * (zk.y - zp.y));
+  const double2 o = make_double2(0.5 * (zk.y + zp.y), -0.5 * (zk.x - zp.x));
+  const double2 to = dmul_conj(o, t);
+  xk = make_double2(e.x + to.x, e.y + to.y);
+  xp = make_double2(e.x - to.x, to.y - e.y);
+}
 
 }  // namespace
 
-__global__ __launch_bounds__(256, 2) void fse_dft64_kernel(BlockArgs<float> a,
-                                                           const double* radial64) {
-  constexpr int WAVES = 4;
-  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  double2* Z = reinterpret_cast<double2*>(smem);          // 64 rows x kDp
-  double2* tw = Z + kFft * kDp;                            // 64 x (cos, sin)
-  double* red = reinterpret_cast<double*>(tw + kFft);      // 4 partial sums
+// Not inlined: its registers are allocated apart from the iteration loop's.
+template <int WAVES>
+__device__ __noinline__ double rerank_transforms(unsigned char* smem, int64_t tw_off,
+                                                 int64_t red_off, const double* radial64,
+                                                 double delta, int M, int N, const float* img,
+                                                 const uint8_t* st, int H, int W, int oy, int ox,
+                                                 double* spec) {
+  constexpr int THREADS = 64 * WAVES;
+  static_assert(THREADS >= 256, "one task per thread in every stage");
+  double2* G = reinterpret_cast<double2*>(smem);  // 64 rows x kHp
+  double* Gd = reinterpret_cast<double*>(smem);
+  const double2* tw = reinterpret_cast<const double2*>(smem + tw_off);
+  double* red = reinterpret_cast<double*>(smem + red_off);  // WAVES partial sums
   const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = uniform_int(tid >> 6);
-  const int M = a.M, N = a.N;
-  const int item = blockIdx.x;
-  const int fw = a.items[2 * item], bij = a.items[2 * item + 1];
-  const int fr = fw & kItemFrameMask;
-  if (fw >> kItemPrioShift) __builtin_amdgcn_s_setprio(2);
-  const int bi = (int)((unsigned)bij >> 16), bj = bij & 0xffff;
-  const FrameDesc fd = a.frames[fr];
-  const float* img = a.work + fd.off;
-  const uint8_t* st = a.state + fd.off;
-  const int oy = bi * a.Bh - a.goy - a.d, ox = bj * a.Bw - a.gox - a.d;
-  double* out = a.spec64 + (int64_t)item * kSpecStride;
-
-  if (tid < kFft) tw[tid] = make_double2(a.twid64[2 * tid], a.twid64[2 * tid + 1]);
+  const int lane = tid & 63, wave = tid >> 6;
   const int n = lane, x = ox + n;
-  const bool xin = n < N && x >= 0 && x < fd.W;
-  const int pp = dpos(lane);
-  const int k2 = lane, c2 = dpos(8 * (k2 & 7) + (k2 >> 3));
+  const bool xin = n < N && x >= 0 && x < W;
   double W0 = 0.0;
-  for (int pass = 0; pass < 2; ++pass) {  // 0: x = f w, 1: w
-    // ---- A: gather and weight; every grid position is written ----
+  for (int pass = 0; pass < 2; ++pass) {  // 0: w, 1: x = f w
+    // ---- A: gather and weight ----
     double wsum = 0.0;
-    for (int m = wave; m < kFft; m += WAVES) {
+    for (int m = wave; m < M; m += WAVES) {
       const int y = oy + m;
       double wv = 0.0, f = 0.0;
-      if (m < M && xin && y >= 0 && y < fd.H) {
-        const int64_t p = (int64_t)y * fd.W + x;
+      if (xin && y >= 0 && y < H) {
+        const int64_t p = (int64_t)y * W + x;
         const uint8_t s = st[p];
-        const double fac = s == kKnown ? 1.0 : (s == kRecon ? a.delta64 : 0.0);
+        const double fac = s == kKnown ? 1.0 : (s == kRecon ? delta : 0.0);
         wv = radial64[m * N + n] * fac;
         f = (double)img[p];
       }
       wsum += wv;
-      Z[m * kDp + dpos(n)] = make_double2(pass ? wv : f * wv, 0.0);
+      Gd[2 * kHp * m + n] = pass ? f * wv : wv;
     }
     if (pass == 0) {
       wsum = wave_sum(wsum);
@@ -861,82 +887,117 @@ __global__ __launch_bounds__(256, 2) void fse_dft64_kernel(BlockArgs<float> a,
     if (pass == 0) {
 #pragma unroll
       for (int q = 0; q < WAVES; ++q) W0 += red[q];
-      if (tid == 0) out[kSpecW0] = W0;
-      if (!(W0 > 0.0)) return;  // uniform
+      if (!(W0 > 0.0)) return 0.0;  // uniform
     }
 
-    // ---- B: rows (only the M rows of the area are non-zero) ----
-    // task (m, n2): 8-point DFT over n1 of z[m][8 n1 + n2], then the twiddle
+    // ---- B: rows; task (m, n2): 8-point DFT over n1 of slot 4 n1 + n2 ----
+    if (tid < 4 * M) {
+      const int m = tid >> 2, n2 = tid & 3;
+      double2* r = G + m * kHp + n2;
+      double2 v[8];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int t = tid + 256 * q, m = t >> 3, n2 = t & 7;
-      if (m < M) {
-        double2* r = Z + m * kDp + n2;
-        double2 v[8];
+      for (int i = 0; i < 8; ++i) v[i] = r[4 * i];
+      dft8(v);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) v[i] = r[9 * i];
-        dft8(v);
+      for (int kk = 1; kk < 8; ++kk) v[kk] = dmul_conj(v[kk], tw[(2 * n2 * kk) & (kFft - 1)]);
 #pragma unroll
-        for (int kk = 1; kk < 8; ++kk) v[kk] = dmul_conj(v[kk], tw[n2 * kk]);
-#pragma unroll
-        for (int i = 0; i < 8; ++i) r[9 * i] = v[i];
-      }
+      for (int i = 0; i < 8; ++i) r[4 * i] = v[i];
     }
     __syncthreads();
-    // task (m, k1): 8-point DFT over n2 of the group k1
+    // task (m, tau): the 4-point DFTs k1 = ka, kb (tau = 0: 0 and 4; else tau
+    // and 8 - tau) give Z[ka + 8 k2] and Z[kb + 8 k2]; their real pairs
+    // (k, 32 - k) are, for tau = 0: (8, 24), (4, 28), (12, 20) and the
+    // self-paired 0 and 16; else (j, 32 - j), (j + 8, 24 - j),
+    // (16 - j, 16 + j), (8 - j, 24 + j) with j = tau
+    if (tid < 4 * M) {
+      const int m = tid >> 2, tau = tid & 3;
+      const bool t0 = tau == 0;
+      const int ka = tau, kb = t0 ? 4 : 8 - tau;
+      double2* ra = G + m * kHp + 4 * ka;
+      double2* rb = G + m * kHp + 4 * kb;
+      double2 za[4], zb[4];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int t = tid + 256 * q, m = t >> 3, k1 = t & 7;
-      if (m < M) {
-        double2* r = Z + m * kDp + 9 * k1;
-        double2 v[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) v[i] = r[i];
-        dft8(v);
-#pragma unroll
-        for (int i = 0; i < 8; ++i) r[i] = v[i];
+      for (int i = 0; i < 4; ++i) {
+        za[i] = ra[i];
+        zb[i] = rb[i];
       }
+      dft4(za[0], za[1], za[2], za[3]);
+      dft4(zb[0], zb[1], zb[2], zb[3]);
+      const int kA = t0 ? 8 : tau, kB = t0 ? 4 : tau + 8, kC = t0 ? 12 : 16 - tau, kD = 8 - tau;
+      double2 x0, x1;
+      real_pair(t0 ? za[1] : za[0], t0 ? za[3] : zb[3], tw[kA], x0, x1);
+      const double2 zkB = t0 ? zb[0] : za[1], zpB = t0 ? zb[3] : zb[2];
+      const double2 zpC = t0 ? zb[2] : za[2];
+      ra[0] = x0;
+      ra[1] = x1;
+      real_pair(zkB, zpB, tw[kB], x0, x1);
+      ra[2] = x0;
+      ra[3] = x1;
+      real_pair(zb[1], zpC, tw[kC], x0, x1);
+      rb[0] = x0;
+      rb[1] = x1;
+      real_pair(zb[0], za[3], tw[kD], x0, x1);
+      if (t0) {  // X[0] and X[32] (both real) share a slot; X[16] = conj Z[16]
+        x0 = make_double2(za[0].x + za[0].y, za[0].x - za[0].y);
+        x1 = dconj(za[2]);
+      }
+      rb[2] = x0;
+      rb[3] = x1;
     }
     __syncthreads();
-    // ---- columns: the same over the row index, one position per lane ----
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int m2 = wave + WAVES * q;
-      double2* c = Z + m2 * kDp + pp;
+
+    // ---- C: columns; task (s, m2): 8-point DFT over m1 of row 8 m1 + m2 ----
+    if (tid < 256) {
+      const int s = tid & 31, m2 = tid >> 5;
+      double2* col = G + s;
       double2 v[8];
 #pragma unroll
       for (int i = 0; i < 8; ++i)
-        v[i] = 8 * i + m2 < M ? c[8 * i * kDp] : make_double2(0.0, 0.0);
+        v[i] = 8 * i + m2 < M ? col[(8 * i + m2) * kHp] : make_double2(0.0, 0.0);
       dft8(v);
 #pragma unroll
       for (int kk = 1; kk < 8; ++kk) v[kk] = dmul_conj(v[kk], tw[m2 * kk]);
 #pragma unroll
-      for (int i = 0; i < 8; ++i) c[8 * i * kDp] = v[i];
+      for (int i = 0; i < 8; ++i) col[(8 * i + m2) * kHp] = v[i];
     }
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int k1 = wave + WAVES * q;
-      double2* c = Z + 8 * k1 * kDp + pp;
+    // task (s, k1): 8-point DFT over m2 of rows 8 k1 ..
+    if (tid < 256) {
+      const int s = tid & 31, k1 = tid >> 5;
+      double2* col = G + 8 * k1 * kHp + s;
       double2 v[8];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) v[i] = c[i * kDp];
+      for (int i = 0; i < 8; ++i) v[i] = col[i * kHp];
       dft8(v);
 #pragma unroll
-      for (int i = 0; i < 8; ++i) c[i * kDp] = v[i];
+      for (int i = 0; i < 8; ++i) col[i * kHp] = v[i];
     }
     __syncthreads();
 
-    // ---- C: out, rows of the spectrum by wavefront ----
-    double2* o = reinterpret_cast<double2*>(out + (pass ? kSpecW : kSpecR0));
-    for (int k1 = wave; k1 < kFft; k1 += WAVES)
-      o[k1 * kFft + k2] = Z[(8 * (k1 & 7) + (k1 >> 3)) * kDp + c2];
-    __syncthreads();  // the grid is free for the next pass
+    // ---- D: out: row K, columns 0..32 (lanes 33.. idle) ----
+    if (lane <= kFft / 2) {
+      const int sl = kHalfSlot[lane];
+      double* o = spec + (pass ? kSpecR0 : kSpecW);
+      for (int K = wave; K < kFft; K += WAVES) {
+        const int Km = (kFft - K) & (kFft - 1);
+        const double2 v = G[(8 * (K & 7) + (K >> 3)) * kHp + sl];
+        double2 e = v;
+        if (lane == 0 || lane == kFft / 2) {  // columns 0 and 32 from the shared slot
+          const double2 vm = G[(8 * (Km & 7) + (Km >> 3)) * kHp + sl];
+          e = lane == 0 ? make_double2(0.5 * (v.x + vm.x), 0.5 * (v.y - vm.y))
+                        : make_double2(0.5 * (v.y + vm.y), -0.5 * (v.x - vm.x));
+        }
+        *reinterpret_cast<double2*>(o + 2 * (K * kHalf + lane)) = e;
+      }
+    }
+    __syncthreads();  // the grid is free (next pass, then the W region)
   }
+  return W0;
 }
 
-// RERANK (T = float only): spectra come from fse_dft64_kernel, and near-tied
-// selections are re-scored exactly in double. Its LDS (about 40 KB at K = 200)
+// RERANK (T = float only): the transforms run in double (rerank_transforms),
+// and near-tied selections are re-scored exactly in double. Its LDS (about 40
+// KB at K = 200)
 // lets four workgroups share a CU, so the register budget is set for 4 (with 4
 // wavefronts) or 8 (with 8 or 16) wavefronts per SIMD.  MX (T = float, 4
 // wavefronts, no re-rank): the transforms run on matrix cores in split f16.
@@ -991,22 +1052,24 @@ fse_block_kernel(BlockArgs<T> a) {
   T wvr[ROWS], wvi[ROWS];
   T W0;
   double W0d = 0.0;
-  const double* spec = nullptr;
+  double* spec = nullptr;  // re-rank: this item's FP64 spectra
   if constexpr (RERANK) {
     spec = a.spec64 + (int64_t)item * kSpecStride;
-    W0d = spec[kSpecW0];
+    W0d = rerank_transforms<WAVES>(smem, L.tw64, L.slots, a.radial64, a.delta64, a.M, a.N, img,
+                                   st, H, W, by0 - a.d, bx0 - a.d, spec);
     W0 = (T)W0d;
-    if (W0d > 0.0) {
+    if (W0d > 0.0) {  // the spectra as floats, back from this block's own writes
 #pragma unroll
       for (int j = 0; j < ROWS; ++j) {
-        const int k = row_of<WAVES, SPLIT>(wave, j) * kFft + lane;
-        rr[j] = (T)spec[kSpecR0 + 2 * k];
-        ri[j] = (T)spec[kSpecR0 + 2 * k + 1];
-        wvr[j] = (T)spec[kSpecW + 2 * k];
-        wvi[j] = (T)spec[kSpecW + 2 * k + 1];
+        const int k1 = row_of<WAVES, SPLIT>(wave, j);
+        const double2 r = half_spec_at(spec + kSpecR0, k1, lane);
+        const double2 w = half_spec_at(spec + kSpecW, k1, lane);
+        rr[j] = (T)r.x;
+        ri[j] = (T)r.y;
+        wvr[j] = (T)w.x;
+        wvi[j] = (T)w.y;
       }
     }
-    __syncthreads();  // twiddles visible
   } else if constexpr (MX) {
     W0 = forward_transforms_mx<T>(smem, L, a.M, a.N, a.radial, a.delta, a.zscale, img, st, H, W,
                                   by0 - a.d, bx0 - a.d, lane, wave, rr, ri, wvr, wvi);
@@ -1158,8 +1221,9 @@ fse_block_kernel(BlockArgs<T> a) {
               for (int c = 0; c < NC; ++c) {
                 kc[c] = (int)((packed >> (12 * c)) & 0xfffull);
                 acc[2 * c] = acc[2 * c + 1] = 0.0;
-                r0r[c] = spec[kSpecR0 + 2 * kc[c]];
-                r0i[c] = spec[kSpecR0 + 2 * kc[c] + 1];
+                const double2 r0 = half_spec_at(spec + kSpecR0, kc[c] >> 6, kc[c] & (kFft - 1));
+                r0r[c] = r0.x;
+                r0i[c] = r0.y;
               }
               // history terms in rounds of kRound x 64 so that all gathers of
               // a round are in flight together (one memory latency per round)
@@ -1174,8 +1238,9 @@ fse_block_kernel(BlockArgs<T> a) {
                   for (int c = 0; c < NC; ++c) {
                     const int d1 = ((kc[c] >> 6) - (uu >> 6)) & (kFft - 1);
                     const int d2 = ((kc[c] & (kFft - 1)) - (uu & (kFft - 1))) & (kFft - 1);
-                    wr[q][c] = spec[kSpecW + 2 * (d1 * kFft + d2)];
-                    wi[q][c] = spec[kSpecW + 2 * (d1 * kFft + d2) + 1];
+                    const double2 wv = half_spec_at(spec + kSpecW, d1, d2);
+                    wr[q][c] = wv.x;
+                    wi[q][c] = wv.y;
                   }
                 }
 #pragma unroll
@@ -1493,16 +1558,6 @@ hipError_t launch_block<float>(const BlockArgs<float>& a, int n_items, int waves
     case 16: return launch_block_w<float, 16, false>(a, n_items, s);
     default: return hipErrorInvalidValue;
   }
-}
-
-// FP64 transform pass of the re-rank mode (one workgroup of 4 wavefronts
-// per work item).
-hipError_t launch_dft64(const BlockArgs<float>& a, const double* radial64, int n_items,
-                        hipStream_t s) {
-  if (n_items <= 0) return hipSuccess;
-  static size_t attr_bytes = 0;
-  const size_t lds = kDftLdsBytes;
-  return launch_with_lds(fse_dft64_kernel, attr_bytes, n_items, 256, lds, s, a, radial64);
 }
 
 template <typename T>

@@ -29,8 +29,6 @@ namespace fse {
 template <typename T>
 hipError_t launch_block(const BlockArgs<T>& a, int n_items, int waves, hipStream_t s, int mode);
 hipError_t upload_twiddle_constants(const double* tbl);
-hipError_t launch_dft64(const BlockArgs<float>& a, const double* radial64, int n_items,
-                        hipStream_t s);
 template <typename T>
 hipError_t launch_scatter(T* work, uint8_t* state, const FrameDesc* frames, const int32_t* items,
                           int n_items, const T* staging, int Bh, int Bw, int gox, int goy,
@@ -646,6 +644,7 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n, bool noallo
   a.state = state;
   a.frames = (const FrameDesc*)pl->frames_dev.ptr;
   a.radial = (const T*)pl->tbl_radial.ptr;
+  a.radial64 = (const double*)pl->tbl_radial64.ptr;
   a.twid = (const T*)pl->tbl_twid.ptr;
   a.twid64 = (const double*)pl->tbl_twid64.ptr;
   a.M = pl->M;
@@ -693,24 +692,24 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n, bool noallo
   int n_launch = 0;
   for (int g = 0; g < G; ++g)
     for (size_t t = 0; t + 1 < gstart[g].size(); ++t) n_launch += gstart[g][t + 1] > gstart[g][t];
-  // timing events (not in the noalloc form): per launch a marker before the
-  // transform pass, one before and one after the iteration kernel; a group's
-  // consecutive launches share the marker between them (every recorded event
-  // is a packet its queue processes between two kernels: three per launch
-  // cost 2-5 % of a batch).  Two more bracket the call's launches.
+  // timing events (not in the noalloc form): a marker before and one after
+  // every launch of the block kernel; a group's consecutive launches share
+  // the marker between them (every recorded event is a packet its queue
+  // processes between two kernels: three per launch cost 2-5 % of a batch).
+  // Two more bracket the call's launches.
   const bool timed = !noalloc;
-  while (timed && (int)pl->events.size() < 3 * n_launch + 2) {
+  while (timed && (int)pl->events.size() < 2 * n_launch + 2) {
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return FSE_ERR_DEVICE;
     pl->events.push_back(e);
   }
-  hipEvent_t ev_fork = timed ? pl->events[3 * n_launch] : nullptr;
-  hipEvent_t ev_end = timed ? pl->events[3 * n_launch + 1] : nullptr;
+  hipEvent_t ev_fork = timed ? pl->events[2 * n_launch] : nullptr;
+  hipEvent_t ev_end = timed ? pl->events[2 * n_launch + 1] : nullptr;
   if (timed && (rc = chk(hipEventRecord(ev_fork, s)))) return rc;  // G > 1 implies timed
   for (int g = 1; g < G; ++g)
     if ((rc = chk(hipStreamWaitEvent(pl->gstreams[g - 1], ev_fork, 0)))) return rc;
   struct LaunchMarks {
-    int pre, mid, post;  // indices into pl->events
+    int pre, post;  // indices into pl->events
   };
   std::vector<LaunchMarks> marks(timed ? n_launch : 0);
   std::vector<int> tail(G, -1);  // marker at the tail of a group's stream, -1 = none
@@ -737,22 +736,11 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n, bool noallo
       if (rerank) a.spec64 = (double*)pl->spec64.ptr + spec_base[g] * kSpecStride;
       const int waves =
           mx ? 4 : (crit_group && g == 0 ? pl->crit_waves_for(cnt) : pl->waves_for(step_total));
-      LaunchMarks m{-1, -1, -1};
+      LaunchMarks m{-1, -1};
       if (timed) {
         if (tail[g] >= 0)
           m.pre = tail[g];
         else if ((rc = mark(gs, m.pre)))
-          return rc;
-      }
-      if constexpr (std::is_same<T, float>::value) {
-        if (rerank &&
-            (rc = chk(launch_dft64(a, (const double*)pl->tbl_radial64.ptr, (int)cnt, gs))))
-          return rc;
-      }
-      if (timed) {
-        if (!rerank)
-          m.mid = m.pre;
-        else if ((rc = mark(gs, m.mid)))
           return rc;
       }
       if ((rc = chk(launch_block<T>(a, (int)cnt, waves, gs, rerank ? 1 : (mx ? 2 : 0)))))
@@ -814,11 +802,10 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n, bool noallo
   std::vector<char> at_ok(at.size(), 0);
   for (size_t i = 0; i < at.size(); ++i)
     at_ok[i] = hipEventElapsedTime(&at[i], ev_fork, pl->events[i]) == hipSuccess;
-  double kms = 0.0, tms = 0.0;
+  double kms = 0.0;
   for (int t = 0; timed && t < n_launch; ++t) {
     const LaunchMarks& m = marks[t];
-    if (at_ok[m.mid] && at_ok[m.post]) kms += at[m.post] - at[m.mid];
-    if (rerank && at_ok[m.pre] && at_ok[m.mid]) tms += at[m.mid] - at[m.pre];
+    if (at_ok[m.pre] && at_ok[m.post]) kms += at[m.post] - at[m.pre];
   }
   float span = 0.f;
   if (timed) (void)hipEventElapsedTime(&span, ev_fork, ev_end);
@@ -829,7 +816,7 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n, bool noallo
     std::vector<std::pair<float, float>> iv;
     iv.reserve(n_launch);
     for (int t = 0; t < n_launch; ++t)
-      if (at_ok[marks[t].mid] && at_ok[marks[t].post]) iv.emplace_back(at[marks[t].mid], at[marks[t].post]);
+      if (at_ok[marks[t].pre] && at_ok[marks[t].post]) iv.emplace_back(at[marks[t].pre], at[marks[t].post]);
     std::sort(iv.begin(), iv.end());
     float lo = 0.f, hi = -1.f;
     for (const auto& x : iv) {
@@ -857,7 +844,7 @@ static int run_batch(fse_plan_s* pl, const fse_frame* frames, int n, bool noallo
     pl->last.rescore_max_wave = (int64_t)cnt[kCntMaxWave];
   }
   pl->last.kernel_ms = kms;
-  pl->last.transform_ms = tms;
+  pl->last.transform_ms = 0.0;  // the transforms run inside the block kernel
   pl->last.span_ms = span;
   pl->last.busy_ms = busy;
   pl->last.groups = G;
@@ -959,10 +946,6 @@ int32_t fse_plan(const fse_params* p, void* hip_stream, fse_plan_t* out) {
       return FSE_ERR_DEVICE;
     }
     pl->own_stream = true;
-  }
-  if (const char* env = std::getenv("GPU_MAX_HW_QUEUES")) {
-    const int q = std::atoi(env);
-    if (q >= 1) pl->hw_queues = q;
   }
   if (const char* env = std::getenv("FSE_FRAME_GROUPS")) {
     const int g = std::atoi(env);
@@ -1121,9 +1104,7 @@ int32_t fse_plan_get_tuning(fse_plan_t pl, fse_tuning* out) {
   out->crit_prio = pl->crit_prio.load() ? 1 : 0;
   {
     const int c = pl->crit_waves.load();
-    out->crit_waves =
-        c >= 0 ? c
-               : (pl->p.precision == FSE_FP32_RERANK || pl->p.precision == FSE_FP64 ? 4 : 0);
+    out->crit_waves = c >= 0 ? c : 4;
   }
   return FSE_OK;
 }

@@ -45,8 +45,6 @@ namespace fse {
 
 template <typename T>
 hipError_t launch_block(const BlockArgs<T>& a, int n_items, int waves, hipStream_t s, int mode);
-hipError_t launch_dft64(const BlockArgs<float>& a, const double* radial64, int n_items,
-                        hipStream_t s);
 template <typename T>
 hipError_t launch_scatter(T* work, uint8_t* state, const FrameDesc* frames, const int32_t* items,
                           int n_items, const T* staging, int Bh, int Bw, int gox, int goy,
@@ -389,6 +387,7 @@ static void worker_loop(Serving* sv) {
   a.trace_u = nullptr;
   a.trace_dc = nullptr;
   a.spec64 = nullptr;
+  a.radial64 = (const double*)pl->tbl_radial64.ptr;
   a.rerank_gap = p.rerank_gap > 0.0 ? p.rerank_gap : 1e-4;
   a.counters = nullptr;
   const bool rerank = p.precision == FSE_FP32_RERANK;
@@ -483,11 +482,6 @@ static void worker_loop(Serving* sv) {
       if (hipMemcpyAsync(stp.items.ptr, stp.host.ptr, n_items * 2 * sizeof(int32_t),
                          hipMemcpyHostToDevice, s) != hipSuccess)
         return fail_all(FSE_ERR_DEVICE);
-      if constexpr (std::is_same<T, float>::value) {
-        if (rerank && launch_dft64(a, (const double*)pl->tbl_radial64.ptr, (int)n_items, s) !=
-                          hipSuccess)
-          return fail_all(FSE_ERR_DEVICE);
-      }
       if (launch_block<T>(a, (int)n_items, waves, s, rerank ? 1 : (mx ? 2 : 0)) != hipSuccess)
         return fail_all(FSE_ERR_DEVICE);
       if (staged && launch_scatter<T>(a.work, a.state, a.frames, a.items, (int)n_items, a.staging,

@@ -109,7 +109,8 @@ def test_destroy_with_frames_in_flight():
 
 
 def test_rerank_spectra_count_against_the_budget():
-    """Re-rank mode's per-step FP64 spectra (131 KB per block of a step) take
+    """Re-rank mode's per-step FP64 spectra (66 KB per block of a step: the
+    columns 0..32 of R0 and W) take
     their share of the budget: with a budget whose share holds 1.5 times the
     largest wave of these frames, the admitted frames' largest waves never
     exceed the share (so not all frames run at once, although their pixels
@@ -118,7 +119,7 @@ def test_rerank_spectra_count_against_the_budget():
     p0 = fse.Params(border_d=14, iterations=40, precision=fse.FSE_FP32_RERANK)
     ref = _alone(p0, frames)
     max_wave = max(a.max_wave_blocks for a in ref)
-    per_block = (4 * 64 * 64 + 32) * 8 + 3 * 8  # FP64 spectra + work items per step block
+    per_block = 4 * 64 * 33 * 8 + 3 * 8  # FP64 spectra + work items per step block
     budget = int(4 * 1.5 * max_wave * per_block)  # a quarter of it is the per-step share
     p = fse.Params(border_d=14, iterations=40, precision=fse.FSE_FP32_RERANK,
                    device_mem_budget=budget, max_inflight_frames=16)
