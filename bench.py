@@ -449,7 +449,7 @@ def main():
         for _ in range(warmup):
             plan.conceal_device(descs)
         torch.cuda.synchronize()
-        kms, tms, busy, launches, blocks, rescored = 0.0, 0.0, 0.0, 0, 0, 0
+        kms, busy, launches, blocks, rescored = 0.0, 0.0, 0, 0, 0
         step_ms = []
         t0 = time.perf_counter()
         for _ in range(steps):
@@ -458,7 +458,6 @@ def main():
             step_ms.append((time.perf_counter() - ts) * 1e3)
             cs = plan.last_call_stats()
             kms += cs["kernel_ms"]
-            tms += cs["transform_ms"]
             busy += cs["busy_ms"]
             launches += cs["launches"]
             blocks += cs["blocks"]
@@ -470,7 +469,7 @@ def main():
                 "median_ms_per_step": float(np.median(step_ms)),
                 "meets_parity_bar": MEETS_BAR[names[precision]],
                 "rescored_iterations_per_step": rescored // steps,
-                "kernel_ms_per_step": kms / steps, "transform_ms_per_step": tms / steps,
+                "kernel_ms_per_step": kms / steps,
                 "kernel_busy_ms_per_step": busy / steps, "groups": cs["groups"],
                 "launches_per_step": launches // steps,
                 "blocks_per_step": blocks // steps, "avg_launch_ms": kms / max(1, launches),
