@@ -340,6 +340,20 @@ class _HostFrame:
         return r
 
 
+class DeviceFrames:
+    """The fse_frame array of a list of device frames (dicts as for
+    Plan.conceal_device), built once so that repeated calls on the same
+    buffers pass it as it is."""
+
+    def __init__(self, frames):
+        self.n = len(frames)
+        self.arr = (_Frame * self.n)()
+        for i, f in enumerate(frames):
+            W, H = int(f["width"]), int(f["height"])
+            self.arr[i] = _Frame(f["image"], W, H, W, f["lost"], W, f["out"], W,
+                                 f.get("out_f32"), f.get("out_f64"), None, None)
+
+
 class Plan:
     """An fse_plan handle.  Use as a context manager or call close()."""
 
@@ -391,13 +405,11 @@ class Plan:
     def conceal_device(self, frames) -> None:
         """Conceal frames whose buffers are device memory.  ``frames`` is a list
         of dicts with integer device pointers and sizes: image, lost, out,
-        width, height (strides = width), optional out_f32 / out_f64."""
-        arr = (_Frame * len(frames))()
-        for i, f in enumerate(frames):
-            W, H = int(f["width"]), int(f["height"])
-            arr[i] = _Frame(f["image"], W, H, W, f["lost"], W, f["out"], W,
-                            f.get("out_f32"), f.get("out_f64"), None, None)
-        _check(self._lib.fse_conceal_image(self.handle, arr, len(frames)), "fse_conceal_image")
+        width, height (strides = width), optional out_f32 / out_f64; or the
+        DeviceFrames of such a list (its fse_frame array built once)."""
+        if not isinstance(frames, DeviceFrames):
+            frames = DeviceFrames(frames)
+        _check(self._lib.fse_conceal_image(self.handle, frames.arr, frames.n), "fse_conceal_image")
 
     def conceal_device_noalloc(self, frames) -> None:
         """conceal_device through fse_conceal_image_noalloc: the call's device

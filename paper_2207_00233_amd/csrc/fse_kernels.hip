@@ -22,9 +22,9 @@
 // complex entries in registers and reads W[k - u] from LDS with a per-lane
 // column offset.  WAVES = 4 is the throughput shape; WAVES = 8 and 16 halve
 // and quarter the serial work per iteration for launches too small to fill
-// the GPU.  The FP64 transform pass of the re-rank mode (fse_dft64_kernel)
-// and the matrix-core transforms (forward_transforms_mx) replace phases A-C
-// and are described where they are defined.
+// the GPU.  The re-rank mode's FP64 transforms (rerank_transforms) and the
+// matrix-core transforms (forward_transforms_mx) replace phases A-C and are
+// described where they are defined.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>

@@ -164,3 +164,19 @@ def test_volume_entry_points_validate_before_touching_the_device(lib):
         assert not h.value
     assert lib.fse_plan3_destroy(None) == fse.FSE_OK
     assert lib.fse_conceal_volume(None, None) == fse.FSE_ERR_INVALID
+
+
+def test_device_frames_marshal_every_field():
+    # the prepared fse_frame array of device frames: pointers and sizes as
+    # given, strides equal to the width, no trace or stats
+    frames = [{"image": 0x1000, "lost": 0x2000, "out": 0x3000, "width": 64, "height": 48},
+              {"image": 0x4000, "lost": 0x5000, "out": 0x6000, "width": 17, "height": 9,
+               "out_f32": 0x7000, "out_f64": 0x8000}]
+    df = fse.DeviceFrames(frames)
+    assert df.n == 2
+    for c, f in zip(df.arr, frames):
+        assert (c.image, c.lost, c.out) == (f["image"], f["lost"], f["out"])
+        assert (c.width, c.height) == (f["width"], f["height"])
+        assert c.stride == c.lost_stride == c.out_stride == f["width"]
+        assert c.out_f32 == f.get("out_f32") and c.out_f64 == f.get("out_f64")
+        assert not c.trace and not c.stats
