@@ -163,14 +163,12 @@ typedef struct {
  * or on 8 wavefronts instead of 4; results equal the oracle's to the same
  * tolerance in every shape, not bit for bit across shapes.
  * FSE_FRAME_GROUPS=g (1..16) sets the number of frame groups of a batched
- * call (default 3 in FSE_FP32_RERANK, 4 when the process runs with
- * GPU_MAX_HW_QUEUES >= 8; 3 in FSE_FP64; else 2).  FSE_CRIT_DEPTH=c (0..1):
- * frames whose schedule has at least c times the waves of the deepest frame
- * form a group of their own, whose workgroups raise their wave priority
- * (FSE_CRIT_PRIO=0 keeps the default priority); 0 = off, default 0.9 in
- * FSE_FP32_RERANK and FSE_FP64, else off.  FSE_CRIT_WAVES=w (4, 8 or 16;
+ * call (default 3).  FSE_CRIT_DEPTH=c (0..1): frames whose schedule has at
+ * least c times the waves of the deepest frame form a group of their own,
+ * whose workgroups raise their wave priority (FSE_CRIT_PRIO=0 keeps the
+ * default priority); 0 = off, default 0.9.  FSE_CRIT_WAVES=w (4, 8 or 16;
  * 0 = by that group's launch size) sets the wavefronts per block of that
- * group (default 4 in FSE_FP32_RERANK).  None of these changes results
+ * group (default 4).  None of these changes results
  * beyond the per-shape rounding noted above.
  */
 int32_t fse_plan(const fse_params *p, void *hip_stream, fse_plan_t *out);
