@@ -1160,8 +1160,6 @@ fse_block_kernel(BlockArgs<T> a) {
         const unsigned long long hit = __ballot(lk == wk);
         const int lw = uniform_int(__builtin_ctzll(hit));
         const int jw = uniform_int(j_of_row<WAVES, SPLIT>(63 - (int)(wk & 63u), wave));
-        const T sr = read_lane((T)rr[jw], lw);
-        const T si = read_lane((T)ri[jw], lw);
         int near = 0;
         if constexpr (RERANK) {
           // 2 when another entry of this wavefront lies within the gap of its
@@ -1173,13 +1171,15 @@ fse_block_kernel(BlockArgs<T> a) {
                            __builtin_popcountll(__ballot(lk >= thr)) >= 2;
           near = two ? 2 : 1;
         }
+        // the lane holding the maximum writes the slot from its own registers
+        // (its key is the wavefront's; the entry by uniform register index)
         FSlot* fs = reinterpret_cast<FSlot*>(smem + L.slots) + (it & 1) * WAVES;
-        if (lane == 0) {
+        if (lane == lw) {
           FSlot v;
-          v.key = wk;
-          v.k = (row_of<WAVES, SPLIT>(wave, jw) << 6) | lw | (near << 12);
-          v.re = sr;
-          v.im = si;
+          v.key = lk;
+          v.k = (row_of<WAVES, SPLIT>(wave, jw) << 6) | lane | (near << 12);
+          v.re = rr[jw];
+          v.im = ri[jw];
           fs[wave] = v;
         }
         __syncthreads();
@@ -1194,15 +1194,19 @@ fse_block_kernel(BlockArgs<T> a) {
         dci = gs * read_lane(mine.im, wwin);
         if constexpr (RERANK) {
           const unsigned thr_g = __float_as_uint(__uint_as_float(gk) * (float)(1.0 - a.rerank_gap));
-          const int contrib =
-              (lane < WAVES && mine.key >= thr_g) ? (mine.k >> 12) : 0;
+          // lanes 0 .. WAVES-1 hold one slot each: the wavefronts whose
+          // maxima lie within the gap of the block maximum, and those among
+          // them that flagged a second entry within the gap of their own
+          const unsigned long long in_gap =
+              __ballot(mine.key >= thr_g) & ((1ull << WAVES) - 1ull);
+          const unsigned long long flagged = __ballot(mine.k >= (2 << 12)) & in_gap;
           // no re-scoring once the float maximum is rounding noise: at or
           // below 2^-40 of the block's first maximum (an all-zero spectrum
           // would otherwise tie every entry)
           const bool live = gk > floor_u;
           if (it == 0) floor_u = (gk >> 23) > 40u ? gk - (40u << 23) : 63u;
-          const bool rerank = live && (__ballot(contrib >= 2) != 0ull ||
-                                       __builtin_popcountll(__ballot(contrib >= 1)) >= 2);
+          const bool rerank =
+              live && (flagged != 0ull || __builtin_popcountll(in_gap) >= 2);
           if (rerank) {  // uniform: every wavefront read the same slots
             // Every wavefront re-scores all of its entries within the gap of
             // the block maximum exactly in double, three at a time (two with
@@ -1337,14 +1341,12 @@ fse_block_kernel(BlockArgs<T> a) {
         }
         jw = uniform_int(jw);
         const int lw = uniform_int(__builtin_ctzll(hit));
-        const T sr = read_lane((T)rr[jw], lw);
-        const T si = read_lane((T)ri[jw], lw);
-        if (lane == 0) {
+        if (lane == lw) {  // the lane holding the maximum writes the slot
           Slot v;
           v.e = wm;
-          v.re = sr;
-          v.im = si;
-          v.k = (row_of<WAVES, SPLIT>(wave, jw) << 6) | lw;
+          v.re = rr[jw];
+          v.im = ri[jw];
+          v.k = (row_of<WAVES, SPLIT>(wave, jw) << 6) | lane;
           sl[wave] = v;
         }
         __syncthreads();
