@@ -334,9 +334,11 @@ int32_t fse_last_call_stats(fse_plan_t plan, fse_call_stats *out);
  * Launch tuning of a plan: how batched calls and serving lay their work on
  * the GPU (results stay within the per-shape rounding noted at fse_plan).
  *   wave_threshold_16  launches of at most this many blocks run on 16
- *                      wavefronts per block (default 128);
+ *                      wavefronts per block (default 128; 0 in
+ *                      FSE_FP32_RERANK);
  *   wave_threshold_8   larger launches of at most this many blocks run on 8
- *                      (default 0: never); all others on 4;
+ *                      (default 0: never; 128 in FSE_FP32_RERANK); all
+ *                      others on 4;
  *   frame_groups       frame groups of a batched call, 1..16; 0 = the
  *                      default, 3;
  *   crit_depth         frames with at least this fraction of the deepest

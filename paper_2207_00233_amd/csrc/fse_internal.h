@@ -96,7 +96,9 @@ struct fse_plan_s {
   // SIMDs idle; more wavefronts per block shorten each block's iteration)
   // (the tuning fields are atomic: fse_plan_set_tuning may change them while
   // the serving worker issues launches).  128: the autotuner's best on the
-  // 64-frame batch in the re-rank and FP32 modes (1-2 % ahead of 256)
+  // 64-frame batch in the FP32 modes (1-2 % ahead of 256); the re-rank mode
+  // takes 0 and 128 instead (fse_plan), measured faster in batches and in
+  // serving
   std::atomic<int> wide_threshold{128};
   std::atomic<int> mid_threshold{0};
   int waves_for(int64_t n_items) const {

@@ -934,6 +934,12 @@ int32_t fse_plan(const fse_params* p, void* hip_stream, fse_plan_t* out) {
     return FSE_ERR_UNSUPPORTED;
   fse_plan_s* pl = new fse_plan_s();
   pl->p = *p;
+  if (p->precision == FSE_FP32_RERANK) {
+    // its small launches on 8 wavefronts instead of 16: the 16-wavefront form
+    // of the re-rank kernel holds its FP64 transforms in 64 VGPRs
+    pl->wide_threshold = 0;
+    pl->mid_threshold = 128;
+  }
   pl->M = M;
   pl->N = N;
   pl->device = dev;

@@ -25,7 +25,7 @@ def test_defaults_and_range_checks():
     with fse.Plan(fse.Params(precision=fse.FSE_FP32_RERANK)) as plan:
         t = plan.get_tuning()
         assert (t["wave_threshold_16"], t["wave_threshold_8"], t["frame_groups"],
-                t["crit_depth"], t["crit_prio"], t["crit_waves"]) == (128, 0, 3, 0.9, 1, 4)
+                t["crit_depth"], t["crit_prio"], t["crit_waves"]) == (0, 128, 3, 0.9, 1, 4)
         for bad in ({"frame_groups": 17}, {"frame_groups": -1}, {"crit_depth": 1.5},
                     {"wave_threshold_16": -1}, {"crit_prio": 2}, {"crit_waves": 2},
                     {"crit_waves": 32}):
@@ -36,7 +36,8 @@ def test_defaults_and_range_checks():
         assert plan.get_tuning() == t
     with fse.Plan(fse.Params(precision=fse.FSE_FP32)) as plan:
         t = plan.get_tuning()
-        assert (t["frame_groups"], t["crit_depth"], t["crit_waves"]) == (3, 0.9, 4)
+        assert (t["wave_threshold_16"], t["wave_threshold_8"], t["frame_groups"],
+                t["crit_depth"], t["crit_waves"]) == (128, 0, 3, 0.9, 4)
     with fse.Plan(fse.Params(precision=fse.FSE_FP64)) as plan:
         t = plan.get_tuning()
         assert (t["frame_groups"], t["crit_depth"], t["crit_waves"]) == (3, 0.9, 4)
