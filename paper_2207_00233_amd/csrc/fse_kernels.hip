@@ -996,13 +996,15 @@ __device__ __noinline__ double rerank_transforms(unsigned char* smem, int64_t tw
 }
 
 // RERANK (T = float only): the transforms run in double (rerank_transforms),
-// and near-tied selections are re-scored exactly in double. Its LDS (about 40
-// KB at K = 200)
-// lets four workgroups share a CU, so the register budget is set for 4 (with 4
-// wavefronts) or 8 (with 8 or 16) wavefronts per SIMD.  MX (T = float, 4
-// wavefronts, no re-rank): the transforms run on matrix cores in split f16.
+// and near-tied selections are re-scored exactly in double.  Its LDS (about
+// 40 KB at K = 200) lets four workgroups share a CU, so with 4 wavefronts the
+// register budget is set for four workgroups (4 wavefronts per SIMD, 128
+// VGPRs); the 8- and 16-wavefront forms serve small launches (a workgroup or
+// two per CU) and get the same 128 VGPRs (two and one workgroups per CU).
+// MX (T = float, 4 wavefronts, no re-rank): the transforms run on matrix
+// cores in split f16.
 template <typename T, int WAVES, bool RERANK, bool MX = false>
-__global__ __launch_bounds__(64 * WAVES, RERANK ? (WAVES == 4 ? 4 : 8) : (MX ? 4 : 1)) void
+__global__ __launch_bounds__(64 * WAVES, RERANK ? (WAVES == 4 ? 4 : 16 / WAVES) : (MX ? 4 : 1)) void
 fse_block_kernel(BlockArgs<T> a) {
   constexpr int THREADS = 64 * WAVES;
   constexpr int ROWS = kFft / WAVES;
