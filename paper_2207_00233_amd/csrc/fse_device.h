@@ -79,7 +79,7 @@ static_assert(kSpecStride * 8 % 256 == 0, "items' spectra stay 256-byte aligned"
 // Byte offsets of the dynamic LDS regions of the fused block kernel with
 // `waves` wavefronts per workgroup (rows = 64 / waves spectrum rows each).
 struct LdsLayout {
-  int64_t cs;        // compact staging (FP64 transform pass): weight classes
+  int64_t cs;        // compact staging (4 wavefronts): weight classes
   int64_t bx, bw;    // phase B: row DFTs of x and w (M x 33 complex each)
   int64_t hist_dc;   // K complex coefficient increments
   int64_t hist_u;    // K selected indices
@@ -93,8 +93,8 @@ struct LdsLayout {
 
 __host__ __device__ inline int64_t align16(int64_t v) { return (v + 15) & ~15LL; }
 
-// `stage` = false for the re-rank iteration kernel, which receives its
-// spectra from the FP64 transform pass and needs no transform staging.
+// `stage_needed` = false for the re-rank kernel, whose FP64 transforms use
+// the W region as their grid (fp64_grid below) instead of the float staging.
 __host__ __device__ inline LdsLayout lds_layout(int M, int N, int K, int waves, int tsize,
                                                 bool stage_needed = true) {
   LdsLayout L;

@@ -782,8 +782,8 @@ __device__ __forceinline__ void load_twiddles(unsigned char* smem, const LdsLayo
 
 // FP64 transforms of the re-rank mode, inside the block kernel: W = DFT(w)
 // and R0 = DFT(x) in double, written to BlockArgs::spec64 for the exact
-// re-scoring and handed to the float iteration (rr/ri in registers, W read
-// back as floats; k1 = row_of(wave, j), k2 = lane).  w and x = f w are real,
+// re-scoring; the block kernel reads its float copies of both back from
+// there (k1 = row_of(wave, j), k2 = lane).  w and x = f w are real,
 // so their spectra are Hermitian (S[-k] = conj S[k]) and columns k2 = 0..32
 // hold all of it: the grid is 64 rows x 32 complex slots (33 KB, inside the
 // block's own LDS).  w and x go through the same steps one after the other (a
@@ -804,9 +804,7 @@ __device__ __forceinline__ void load_twiddles(unsigned char* smem, const LdsLayo
 //     (output row 8 (K & 7) + (K >> 3) holds frequency K); the shared slot
 //     transforms X[.][0] + j X[.][32], whose two columns are separated on the
 //     way out;
-//  D: out: row K of the spectrum, columns 0..32, to HBM (and for x the
-//     lane's entries, columns above 32 from the conjugate entry, to
-//     registers).
+//  D: out: row K of the spectrum, columns 0..32, to HBM.
 // Returns W0 (0 when the area has no support: nothing is written then).
 constexpr int kHp = 33;  // grid pitch in complex doubles (one pad slot)
 static_assert(kFft * kHp * 16 <= (kFft + 3) * kFft * 8,
